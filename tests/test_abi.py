@@ -1,0 +1,146 @@
+"""The C ABI on the host: the library loads, exports every symbol gw.h
+declares, answers workspace queries, and rejects invalid arguments with the
+documented status before launching anything (no GPU needed).  Fake device
+pointers are only used in calls whose validation must fail."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gw.h")
+LIB = os.path.join(ROOT, "paper_1003_0316_amd", "libgw.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libgw.so not built")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gw_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_1003_0316_amd import binding
+    return binding
+
+
+def test_exports_every_declared_symbol(b):
+    names = header_functions()
+    assert "gw_polarization" in names and "gw_screen" in names and "gw_project" in names
+    for n in names:
+        assert hasattr(b.lib(), n), n
+    assert set(b.EXPORTED) <= set(names)
+
+
+def test_version(b):
+    assert b.gw_version() >= 100
+
+
+def _desc(b, n_k=2, N=8, R=16, n_occ=2, n_unocc=3, omega=(0.0, 1.0), eps=None, precision=0):
+    keep = {}
+    d = b.GwPolDesc()
+    d.precision, d.n_k, d.N, d.R, d.n_occ, d.n_unocc = precision, n_k, N, R, n_occ, n_unocc
+    d.occ_begin, d.occ_end, d.unocc_begin, d.unocc_end = 0, n_occ, 0, n_unocc
+    keep["om"] = np.asarray(omega, dtype=np.float64)
+    d.n_omega = len(omega)
+    d.omega_host = keep["om"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if eps is None:
+        eps = np.concatenate([np.linspace(-0.5, -0.1, n_occ), np.linspace(0.1, 1.0, n_unocc)])
+        eps = np.tile(eps, (n_k, 1))
+    keep["eps"] = np.ascontiguousarray(eps, dtype=np.float64)
+    d.eps_host = keep["eps"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    fake = 0x7F0000001000   # never dereferenced: every call below fails validation first
+    d.U = d.psi = d.eps = d.P = fake
+    d.kq_host = None
+    d.k_list_host = None
+    return d, keep
+
+
+def test_workspace_queries(b):
+    d, keep = _desc(b)
+    n = ctypes.c_size_t(0)
+    assert b.lib().gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(n)) == 0
+    assert n.value >= 8 * 6 * 16
+    assert b.gw_screen_workspace_size(100, 3) > 0
+    assert b.gw_project_workspace_size("fp64", 4, 4, 1, 1) == 0
+
+
+def _status(b, d):
+    return b.lib().gw_polarization(None, ctypes.byref(d), ctypes.c_void_p(0x7F0000002000), 1 << 40)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("N", 0), ("R", -1), ("n_omega", 0), ("occ_begin", 5), ("unocc_end", 9), ("precision", 7),
+])
+def test_rejects_bad_sizes(b, field, value):
+    d, keep = _desc(b)
+    setattr(d, field, value)
+    assert _status(b, d) == -1
+    assert b.gw_last_error() != ""
+
+
+def test_rejects_negative_frequency(b):
+    d, keep = _desc(b, omega=(0.0, -1.0))
+    assert _status(b, d) == -1
+    assert "frequenc" in b.gw_last_error()
+
+
+def test_rejects_metal(b):
+    eps = np.tile([-0.5, 0.3, 0.2, 0.4, 0.9], (2, 1))  # occupied 0.3 above unoccupied 0.2
+    d, keep = _desc(b, eps=eps)
+    assert _status(b, d) == -1
+    assert "insulator" in b.gw_last_error()
+
+
+def test_rejects_bad_k_maps(b):
+    d, keep = _desc(b)
+    kq = np.array([1, 5], dtype=np.int32)
+    d.kq_host = kq.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    assert _status(b, d) == -1
+    d, keep = _desc(b)
+    kl = np.array([0, 2], dtype=np.int32)
+    d.k_list_host = kl.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    d.n_k_list = 2
+    assert _status(b, d) == -1
+
+
+def test_rejects_too_many_frequencies(b):
+    d, keep = _desc(b, omega=tuple(np.linspace(0, 1, 65)))
+    assert _status(b, d) == -2
+
+
+def test_rejects_small_workspace(b):
+    d, keep = _desc(b)
+    st = b.lib().gw_polarization(None, ctypes.byref(d), ctypes.c_void_p(0x7F0000002000), 16)
+    assert st == -3
+    st = b.lib().gw_polarization(None, ctypes.byref(d), None, 0)
+    assert st == -3
+
+
+def test_rejects_null_pointers(b):
+    d, keep = _desc(b)
+    d.P = None
+    assert _status(b, d) == -1
+    assert b.lib().gw_polarization(None, None, None, 0) == -1
+
+
+def test_screen_validation(b):
+    L = b.lib()
+    fake = ctypes.c_void_p(0x7F0000003000)
+    assert L.gw_screen(None, 0, 1, fake, fake, fake, fake, fake, 1 << 30) == -1
+    assert L.gw_screen(None, 4, 1, None, fake, fake, fake, fake, 1 << 30) == -1
+    assert L.gw_screen(None, 4, 1, fake, fake, fake, fake, fake, 1 << 30) == -1  # W aliases P
+    other = ctypes.c_void_p(0x7F0000004000)
+    assert L.gw_screen(None, 4, 1, fake, fake, other, fake, fake, 8) == -3
+
+
+def test_project_validation(b):
+    L = b.lib()
+    fake = ctypes.c_void_p(0x7F0000003000)
+    assert L.gw_project(None, 0, 0, 4, 1, 1, fake, fake, fake, fake, None, 0) == -1
+    assert L.gw_project(None, 9, 4, 4, 1, 1, fake, fake, fake, fake, None, 0) == -1
+    assert L.gw_project(None, 0, 4, 4, 1, 1, None, fake, fake, fake, None, 0) == -1
