@@ -1,0 +1,132 @@
+"""Reduced-precision HIP paths (FP32 MFMA, split BF16, split FP16) vs the CPU
+FP64 oracle on the same complex64-rounded inputs; tolerance 1e-4 relative
+Frobenius error per frequency (the reduced-precision bar), measured values are
+printed.  Shapes span several 128-wide tiles and ragged tails."""
+import numpy as np
+import pytest
+
+import gwsynth
+from oracle import polarization as orc
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+PRECS = ["fp32", "split_bf16", "split_fp16"]
+
+
+def _dev(inp):
+    import torch
+    U = torch.from_numpy(np.ascontiguousarray(inp.U)).to("cuda", torch.complex64)
+    psi = torch.from_numpy(np.ascontiguousarray(inp.psi)).to("cuda", torch.complex64)
+    return U, psi
+
+
+def _rounded(inp):
+    """The c64 values the GPU receives, widened to c128 for the oracle."""
+    return inp.U.astype(np.complex64).astype(np.complex128), inp.psi.astype(np.complex64).astype(np.complex128)
+
+
+def _supported(lib, prec):
+    try:
+        lib.gw_project_workspace_size(prec, 4, 4, 1, 1)
+        return True
+    except lib.GwError:
+        return False
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_project_ragged(lib, prec):
+    import torch
+    shp = gwsynth.make_shape(n_k=1, n_b=50, R=1000, N=300, n_occ=3, n_unocc=50)
+    inp = gwsynth.generate(shp, seed=31)
+    U, psi = _dev(inp)
+    M = lib.gw_project(U, psi[0, :3].contiguous(), psi[0, 3:].contiguous(), prec)
+    torch.cuda.synchronize()
+    Ur, pr = _rounded(inp)
+    ref = orc.projections(Ur, pr[0, :3], pr[0, 3:])
+    err = np.linalg.norm(M.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"{prec} projection rel err {err:.2e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", [
+    dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150),
+    dict(n_k=1, n_b=20, R=33, N=7, n_occ=1, n_unocc=5),
+    dict(n_k=3, n_b=64, R=512, N=129, n_occ=2, n_unocc=63),
+])
+def test_polarization_ragged(lib, prec, shape):
+    import torch
+    inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=9, omega=gwsynth.omega_mesh("m16"))
+    U, psi = _dev(inp)
+    P = lib.gw_polarization(U, psi, inp.eps, inp.omega, shape["n_occ"], precision=prec, kq=inp.kq)
+    torch.cuda.synchronize()
+    Ur, pr = _rounded(inp)
+    ref = orc.polarization(Ur, pr, inp.eps, inp.omega, shape["n_occ"], kq=inp.kq)
+    Pg = P.cpu().numpy()
+    err = orc.rel_fro(Pg, ref)
+    print(f"{prec} {shape} max rel err {err.max():.2e}")
+    assert err.max() < TOL, err
+    for j in range(Pg.shape[0]):
+        assert np.array_equal(Pg[j], Pg[j].conj().T)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_polarization_chunked_matches_unchunked(lib, prec):
+    """Chunk size only changes where FP32 partial sums are flushed to FP64."""
+    import torch
+    inp = gwsynth.generate(gwsynth.make_shape(n_k=2, n_b=40, R=256, N=150, n_occ=4, n_unocc=40), seed=3,
+                           omega=gwsynth.omega_mesh("c1"))
+    U, psi = _dev(inp)
+    P1 = lib.gw_polarization(U, psi, inp.eps, inp.omega, 4, precision=prec, kq=inp.kq).clone()
+    P2 = lib.gw_polarization(U, psi, inp.eps, inp.omega, 4, precision=prec, kq=inp.kq, chunk_pairs=37).clone()
+    torch.cuda.synchronize()
+    d = orc.rel_fro(P1.cpu().numpy(), P2.cpu().numpy())
+    assert d.max() < 1e-5
+
+
+def test_config2_fp32_sampled_k(lib):
+    """Config 2 (N_k=64, N=500, R=4096, 16 occ + 500 unocc, 13 frequencies) on
+    two sampled k-points: FP32 GPU vs FP64 oracle, then W in FP64."""
+    import torch
+    inp = gwsynth.generate("c2")
+    U, psi = _dev(inp)
+    ks = [0, 37]
+    P = lib.gw_polarization(U, psi, inp.eps, inp.omega, 16, precision="fp32", kq=inp.kq, k_list=ks)
+    W, info = lib.gw_screen(P, torch.from_numpy(inp.v).to("cuda"))
+    torch.cuda.synchronize()
+    Ur, pr = _rounded(inp)
+    ref = orc.polarization(Ur, pr, inp.eps, inp.omega, 16, kq=inp.kq, k_list=ks)
+    err = orc.rel_fro(P.cpu().numpy(), ref)
+    Wref = orc.screened_interaction(ref, inp.v)
+    werr = orc.rel_fro(W.cpu().numpy(), Wref)
+    print(f"config2 fp32 k={ks}: P err max {err.max():.2e}, W err max {werr.max():.2e}")
+    assert int(info.abs().sum()) == 0
+    assert err.max() < TOL and werr.max() < TOL
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_deterministic(lib, prec):
+    import torch
+    inp = gwsynth.generate("c1")
+    U, psi = _dev(inp)
+    P1 = lib.gw_polarization(U, psi, inp.eps, inp.omega, 4, precision=prec, kq=inp.kq).clone()
+    P2 = lib.gw_polarization(U, psi, inp.eps, inp.omega, 4, precision=prec, kq=inp.kq).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(P1, P2)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_poisoned_workspace(lib, prec):
+    """The result does not depend on stale workspace contents."""
+    import torch
+    inp = gwsynth.generate("c1")
+    U, psi = _dev(inp)
+    call = lib.PolarizationCall(U, psi, inp.eps, inp.omega, 4, precision=prec, kq=inp.kq)
+    n = call.workspace_size()
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ws.fill_(0)
+    P1 = call.run(ws).clone()
+    ws.fill_(0xFF)   # NaN patterns everywhere
+    P2 = call.run(ws).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(P1, P2)
