@@ -24,12 +24,12 @@ Two backends draw the same recipe:
 * ``numpy`` -- everything on the host, bit-reproducible per seed.  Seeds:
   ``SeedSequence([20100316, cfg_id]).spawn(N_k + 1)``; child k draws, in this
   order, Re A, Im A, Re z, Im z, eps_occ, eps_unocc; child N_k draws Re U, Im U.
-* ``torch`` -- for the large workloads: the big Gaussian arrays (A, U) are drawn
+* ``torch`` -- for the large workloads: the Gaussian arrays (A, z, U) are drawn
   on the device with torch's counter-based generator seeded from the same
-  SeedSequence children; z and the energies still come from numpy on the host.
-  The matrix product z^T A runs in complex64 on the device.  Values differ from
-  the numpy backend; each run's oracle consumes the very tensors the GPU path
-  consumes.
+  SeedSequence children; the energies still come from numpy on the host.  z is
+  orthonormalised by a complex128 QR and z^T A runs in complex64, both on the
+  device.  Values differ from the numpy backend; each run's oracle consumes the
+  very tensors the GPU path consumes.
 """
 from __future__ import annotations
 
@@ -168,13 +168,16 @@ def generate(shape: Shape | str, seed: Optional[int] = None, *, omega: Optional[
 def generate_torch(shape: Shape | str, device, seed: Optional[int] = None, *,
                    omega: Optional[Sequence[float]] = None, base_seed: int = BASE_SEED,
                    k_subset: Optional[Sequence[int]] = None,
-                   band_limit: Optional[int] = None) -> Inputs:
+                   band_limit: Optional[int] = None, log=None) -> Inputs:
     """Device generation in complex64 (large workloads).
 
-    ``band_limit`` keeps only the first ``band_limit`` bands of each k-set (the
-    occupied ones and the lowest unoccupied ones); the basis z is still drawn and
-    orthonormalised at full width so the kept bands are the same as in a full
-    draw.  ``k_subset`` generates only those k-sets (others left as zeros).
+    Gaussian draws use torch's device generator seeded from the SeedSequence
+    children; the energies come from numpy on the host.  The orthonormal
+    basis z is computed blockwise by a complex128 QR on the device, and
+    psi_k = z^T A / sqrt(N_b) by complex64 products.  ``band_limit`` keeps the
+    first ``band_limit`` bands of each k-set (z is still drawn and
+    orthonormalised at full width, so the kept bands equal those of a full
+    draw); ``k_subset`` generates only those k-sets (others stay zero).
     """
     import torch
 
@@ -187,41 +190,48 @@ def generate_torch(shape: Shape | str, device, seed: Optional[int] = None, *,
     nb = nb_full if band_limit is None else min(nb_full, band_limit)
     psi = torch.zeros((shape.n_k, nb, shape.R), dtype=torch.complex64, device=device)
     eps = np.zeros((shape.n_k, nb_full), dtype=np.float64)
-    ks = range(shape.n_k) if k_subset is None else sorted(set(k_subset))
+    ks = set(range(shape.n_k)) if k_subset is None else set(k_subset)
     scale = 1.0 / math.sqrt(shape.n_b)
+
+    def cn(g, rows, cols, dtype=torch.float32):
+        x = torch.complex(torch.randn((rows, cols), generator=g, device=device, dtype=dtype),
+                          torch.randn((rows, cols), generator=g, device=device, dtype=dtype))
+        return x.mul_(math.sqrt(0.5))
+
     for k in range(shape.n_k):
         rng = np.random.default_rng(children[k])
         dev_seed = int(rng.integers(0, 2**62))
-        zraw = _cn(rng, (shape.n_b, nb_full))
         eps[k, :shape.n_occ] = np.sort(rng.uniform(-0.5, 0.0, shape.n_occ))
         eps[k, shape.n_occ:] = np.sort(rng.uniform(0.02, 2.0, shape.n_unocc))
         if k not in ks:
             continue
-        z = _orthonormal_columns(zraw)[:, :nb]
         g = torch.Generator(device=device)
         g.manual_seed(dev_seed)
-        zt = torch.from_numpy(np.ascontiguousarray(z.T)).to(device=device, dtype=torch.complex64)
-        # A is drawn in row blocks to bound the transient footprint.
+        zraw = cn(g, shape.n_b, nb_full, torch.float64)
+        z = torch.empty_like(zraw)
+        for c0 in range(0, nb_full, shape.n_b):
+            c1 = min(nb_full, c0 + shape.n_b)
+            q, _ = torch.linalg.qr(zraw[:, c0:c1], mode="reduced")
+            z[:, c0:c1] = q
+        zt = z[:, :nb].transpose(0, 1).contiguous().to(torch.complex64)
+        del zraw, z
         acc = None
         rb = 1024
         for r0 in range(0, shape.n_b, rb):
             r1 = min(shape.n_b, r0 + rb)
-            Ablk = torch.complex(torch.randn((r1 - r0, shape.R), generator=g, device=device),
-                                 torch.randn((r1 - r0, shape.R), generator=g, device=device))
-            Ablk.mul_(math.sqrt(0.5))
+            Ablk = cn(g, r1 - r0, shape.R)
             part = torch.matmul(zt[:, r0:r1].contiguous(), Ablk)
             acc = part if acc is None else acc.add_(part)
             del Ablk, part
         psi[k].copy_(acc.mul_(scale))
         del acc, zt
+        if log:
+            log(f"generated k-set {k}")
     rng = np.random.default_rng(children[shape.n_k])
-    useed = int(rng.integers(0, 2**62))
     g = torch.Generator(device=device)
-    g.manual_seed(useed)
-    U = torch.complex(torch.randn((shape.N, shape.R), generator=g, device=device),
-                      torch.randn((shape.N, shape.R), generator=g, device=device))
-    dec = torch.from_numpy(_u_decay(shape.N, shape.R) * math.sqrt(0.5)).to(device=device,
-                                                                            dtype=torch.float32)
+    g.manual_seed(int(rng.integers(0, 2**62)))
+    U = cn(g, shape.N, shape.R)
+    dec = torch.from_numpy(_u_decay(shape.N, shape.R)).to(device=device, dtype=torch.float32)
     U.mul_(dec[:, None])
     om = np.asarray(omega, dtype=np.float64) if omega is not None else omega_mesh(shape.omega)
     kq = ((np.arange(shape.n_k) + 1) % shape.n_k).astype(np.int32)

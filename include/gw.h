@@ -147,6 +147,21 @@ int gw_screen_workspace_size(int N, int n_omega, size_t* bytes_host);
 int gw_screen(void* stream, int N, int n_omega, const double* P, const double* v, double* W,
               int* info, void* ws, size_t ws_bytes);
 
+
+/* ------------------------------------------------------------------ profiling
+ * Optional per-kernel timing with HIP events recorded on the caller's stream
+ * around every launch of the library's main kernels (projection,
+ * accumulation, screening update, ...).  Off by default.
+ *   gw_profile_enable(1) starts recording, gw_profile_enable(0) stops.
+ *   gw_profile_reset() drops all records.
+ *   gw_profile_query(name, &launches, &total_ms) synchronises the recorded
+ *   events and sums the durations of the launches of kernel `name` (the
+ *   kernel's function name, e.g. "project_bf16_kernel"); unknown names give
+ *   launches = 0.  Host-side bookkeeping only; safe to call from one thread. */
+int gw_profile_enable(int on);
+int gw_profile_reset(void);
+int gw_profile_query(const char* kernel_name_host, int* launches_host, double* total_ms_host);
+
 #ifdef __cplusplus
 }
 #endif

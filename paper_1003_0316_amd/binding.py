@@ -65,8 +65,13 @@ _lib.gw_polarization.argtypes = [_vp, ctypes.POINTER(GwPolDesc), _vp, _sz]
 _lib.gw_screen_workspace_size.argtypes = [_ci, _ci, ctypes.POINTER(_sz)]
 _lib.gw_screen.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp, _vp, _vp, _sz]
 
+_lib.gw_profile_enable.argtypes = [_ci]
+_lib.gw_profile_reset.argtypes = []
+_lib.gw_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(_ci), ctypes.POINTER(ctypes.c_double)]
+
 EXPORTED = ("gw_last_error", "gw_version", "gw_project_workspace_size", "gw_project",
-            "gw_polarization_workspace_size", "gw_polarization", "gw_screen_workspace_size", "gw_screen")
+            "gw_polarization_workspace_size", "gw_polarization", "gw_screen_workspace_size", "gw_screen",
+            "gw_profile_enable", "gw_profile_reset", "gw_profile_query")
 
 
 def lib():
@@ -255,3 +260,19 @@ def gw_screen(P: torch.Tensor, v: torch.Tensor, W: Optional[torch.Tensor] = None
     _check(_lib.gw_screen(_stream(stream), N, n_om, P.data_ptr(), v.data_ptr(), W.data_ptr(), info.data_ptr(),
                           ws.data_ptr(), ws.numel()))
     return W, info
+
+
+def gw_profile_enable(on: bool = True) -> None:
+    _check(_lib.gw_profile_enable(1 if on else 0))
+
+
+def gw_profile_reset() -> None:
+    _check(_lib.gw_profile_reset())
+
+
+def gw_profile_query(kernel: str):
+    """(launches, total_ms) of the recorded launches of `kernel` (synchronises)."""
+    n = ctypes.c_int(0)
+    ms = ctypes.c_double(0.0)
+    _check(_lib.gw_profile_query(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

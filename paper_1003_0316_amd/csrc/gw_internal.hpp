@@ -46,6 +46,21 @@ struct Carver {
   }
 };
 
+// ---- optional launch timing (gw_profile_*) ----------------------------------------
+class ProfScope {
+ public:
+  ProfScope(hipStream_t s, const char* name);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  hipStream_t s_;
+  const char* name_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+  bool active_ = false;
+};
+
 // ---- transition-pair chunk ---------------------------------------------------
 // A chunk is a block of occupied bands [n0, n0+no) of set k times the
 // unoccupied bands [u0, u0+nu) of set kq; pair t = (n-n0)*nu + (n'-u0).

@@ -239,6 +239,7 @@ int launch_project_f64(hipStream_t s, int N, int R, const double2* U, const doub
                        const double2* pu, int no, int nu, double2* M, long ldm) {
   int T = no * nu;
   dim3 grid((T + TN - 1) / TN, (N + TM - 1) / TM);
+  ProfScope prof(s, "project_f64_kernel");
   hipLaunchKernelGGL(project_f64_kernel, grid, dim3(NT), 0, s, N, R, U, po, pu, no, nu, M, ldm);
   GW_LAUNCHED("project_f64_kernel");
   return GW_OK;
@@ -248,6 +249,7 @@ int launch_herk_f64(hipStream_t s, int N, int T, const double2* M, long ldm, con
                     double2* P) {
   int nb = (N + TM - 1) / TM;
   dim3 grid(nb * (nb + 1) / 2, n_omega);
+  ProfScope prof(s, "herk_f64_kernel");
   hipLaunchKernelGGL(herk_f64_kernel, grid, dim3(NT), 0, s, N, T, M, ldm, w, P);
   GW_LAUNCHED("herk_f64_kernel");
   return GW_OK;

@@ -269,6 +269,7 @@ int screen_run(hipStream_t s, int N, int n_omega, const double2* P, const double
     GW_LAUNCHED("pivot_kernel");
     hipLaunchKernelGGL(panel_kernel, dim3(nb, n_omega), dim3(NT), 0, s, N, c0, bp, W, Dbuf, Cbuf, Obuf, info);
     GW_LAUNCHED("panel_kernel");
+    ProfScope prof(s, "update_kernel");
     hipLaunchKernelGGL(update_kernel, dim3(ntiles, n_omega), dim3(NT), 0, s, N, c0, bp, W, Dbuf, Cbuf, Obuf,
                        info);
     GW_LAUNCHED("update_kernel");
