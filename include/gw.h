@@ -148,6 +148,88 @@ int gw_screen(void* stream, int N, int n_omega, const double* P, const double* v
               int* info, void* ws, size_t ws_bytes);
 
 
+/* ----------------------------------------------------------- learned high-band part
+ * The unoccupied bands above a cutoff are left out of the explicit sum and
+ * their contribution to P is predicted by a small perceptron (the paper's
+ * extrapolar correction, text after Eq. SEc_AC / Fig. nband, targets the same
+ * truncation with a fixed-energy completeness argument; here the correction is
+ * learned from full-band runs).
+ *
+ * Perceptron: h1 = silu(x W1 + b1), h2 = silu(h1 W2 + b2), y = h2 W3 + b3,
+ * silu(z) = z sigmoid(z).  Parameters live in caller-owned device buffers:
+ *   master  FP32 [W1 n_in*width][b1 width][W2 width*width][b2 width]
+ *                [W3 width*n_out][b3 n_out], each W row-major [in][out]
+ *   adam_m, adam_v  FP32, same layout (needed by gw_mlp_adam_step only)
+ *   wt      BF16 copies of W1, W2, W3 transposed ([out][in]), concatenated
+ *   wk      BF16 copies of W1, W2, W3 in master layout ([in][out])
+ * n_in, width, n_out are each 32, 64, 128 or 256.  Matrix products use the
+ * BF16 weights with FP32 accumulation; FP32 activations and gradients enter
+ * as hi + lo BF16 pairs.  Row-major FP32 buffers must be 16-byte aligned. */
+typedef struct gw_mlp {
+  int n_in, width, n_out;
+  float* master;
+  float* adam_m;
+  float* adam_v;
+  uint16_t* wt;
+  uint16_t* wk;
+} gw_mlp;
+
+/* Element counts of master (and of adam_m/adam_v) and of wt (= of wk). */
+int gw_mlp_sizes(int n_in, int width, int n_out, size_t* n_params_host, size_t* n_bf16_host);
+/* Refresh wt and wk from master (after loading or editing master). */
+int gw_mlp_sync_bf16(void* stream, const gw_mlp* m_host);
+/* Y [rows][n_out] from X [rows][n_in]; act (4*rows*width floats) receives
+ * the blocks z1, h1, z2, h2, each [rows][width], for gw_mlp_backward. */
+int gw_mlp_forward(void* stream, const gw_mlp* m_host, const float* X, int rows, float* Y, float* act);
+/* loss[0] = (1/rows) sum 0.5 mask (Y - T)^2 over the first n_used columns of
+ * Y [rows][n_out]; T and mask are [rows][n_used] (mask may be NULL);
+ * dY [rows][n_out] = mask (Y - T) / rows (zero in unused columns). */
+int gw_mlp_loss(void* stream, int rows, int n_out, int n_used, const float* Y, const float* T, const float* mask,
+                float* dY, float* loss);
+int gw_mlp_workspace_size(int rows, int width, size_t* bytes_host);
+/* grad (master layout) = d loss / d params for the loss whose dY is given;
+ * dX [rows][n_in] optional (NULL to skip).  act from gw_mlp_forward. */
+int gw_mlp_backward(void* stream, const gw_mlp* m_host, const float* X, const float* act, const float* dY, int rows,
+                    float* grad, float* dX, void* ws, size_t ws_bytes);
+/* One Adam step (Kingma & Ba, bias-corrected, step counts from 1) on master;
+ * refreshes wt and wk. */
+int gw_mlp_adam_step(void* stream, const gw_mlp* m_host, const float* grad, float lr, float beta1, float beta2,
+                     float eps, int step);
+
+/* Inputs of the feature, judge and correction kernels.  P_ret is the explicit
+ * sum over unoccupied bands [0, cut) (from gw_polarization). */
+typedef struct gw_surr_desc {
+  int N, n_omega;
+  const double* omega_host;  /* [n_omega]; the first entry is the reference frequency */
+  int n_k, n_occ, n_unocc;   /* band layout as in gw_pol_desc */
+  int cut;                   /* explicit unoccupied bands, 1 <= cut <= n_unocc */
+  const int* kq_host;        /* NULL means (k+1) mod n_k; n_k <= 64 */
+  const double* eps;         /* device [n_k][n_occ+n_unocc] */
+  const double* P_ret;       /* device [n_omega][N][N] c128 */
+  int n_in;                  /* feature row length (multiple of 32, >= 12) */
+} gw_surr_desc;
+
+int gw_surrogate_workspace_size(const gw_surr_desc* d_host, size_t* bytes_host);
+/* X [n_omega*N][n_in], row r = j*N + I: 12 features of basis function I at
+ * frequency j (omega map, log of the left-out/retained weight sums of the
+ * band energies, log profile and relative size of |P_ret,II|, I/N, band-edge
+ * energies, retained fraction), zero padded. */
+int gw_surrogate_features(void* stream, const gw_surr_desc* d_host, float* X, void* ws, size_t ws_bytes);
+/* Training targets: T[r] = log((P_ret,II - P_full,II) / |P_ret,II|), mask 0
+ * where undefined.  T and mask are [n_omega*N]. */
+int gw_surrogate_targets(void* stream, int N, int n_omega, const double* P_ret, const double* P_full, float* T,
+                         float* mask);
+/* P_j[I][J] *= 1 + exp((y_jI + y_jJ)/2) with y_jI = Y[(j*N + I)*ldy]
+ * (y clamped to [-30, 30]): P + D P D, D = diag(exp(y/2)). */
+int gw_surrogate_apply(void* stream, int N, int n_omega, const float* Y, int ldy, double* P);
+/* err[j] (device, n_omega doubles) = |TRs_j / f_j - TRp_j| / TRp_j with TRp
+ * the predicted left-out trace, TRs the trace of P_sample (the explicit sum of
+ * the left-out bands [cut, n_unocc) for the sample rows (k, occupied band)
+ * given) and f_j the sample's share of the left-out weight sum. */
+int gw_surrogate_judge(void* stream, const gw_surr_desc* d_host, const float* Y, int ldy, const double* P_sample,
+                       int n_sample, const int* sample_k_host, const int* sample_occ_host, double* err, void* ws,
+                       size_t ws_bytes);
+
 /* ------------------------------------------------------------------ profiling
  * Optional per-kernel timing with HIP events recorded on the caller's stream
  * around every launch of the library's main kernels (projection,

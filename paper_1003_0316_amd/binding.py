@@ -65,13 +65,46 @@ _lib.gw_polarization.argtypes = [_vp, ctypes.POINTER(GwPolDesc), _vp, _sz]
 _lib.gw_screen_workspace_size.argtypes = [_ci, _ci, ctypes.POINTER(_sz)]
 _lib.gw_screen.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp, _vp, _vp, _sz]
 
+class GwMlp(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int), ("width", ctypes.c_int), ("n_out", ctypes.c_int),
+                ("master", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("wt", ctypes.c_void_p), ("wk", ctypes.c_void_p)]
+
+
+class GwSurrDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("n_omega", ctypes.c_int), ("omega_host", ctypes.POINTER(ctypes.c_double)),
+                ("n_k", ctypes.c_int), ("n_occ", ctypes.c_int), ("n_unocc", ctypes.c_int), ("cut", ctypes.c_int),
+                ("kq_host", ctypes.POINTER(ctypes.c_int)), ("eps", ctypes.c_void_p), ("P_ret", ctypes.c_void_p),
+                ("n_in", ctypes.c_int)]
+
+
+_pm = ctypes.POINTER(GwMlp)
+_ps = ctypes.POINTER(GwSurrDesc)
+_f = ctypes.c_float
+_lib.gw_mlp_sizes.argtypes = [_ci, _ci, _ci, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]
+_lib.gw_mlp_sync_bf16.argtypes = [_vp, _pm]
+_lib.gw_mlp_forward.argtypes = [_vp, _pm, _vp, _ci, _vp, _vp]
+_lib.gw_mlp_loss.argtypes = [_vp, _ci, _ci, _ci, _vp, _vp, _vp, _vp, _vp]
+_lib.gw_mlp_workspace_size.argtypes = [_ci, _ci, ctypes.POINTER(_sz)]
+_lib.gw_mlp_backward.argtypes = [_vp, _pm, _vp, _vp, _vp, _ci, _vp, _vp, _vp, _sz]
+_lib.gw_mlp_adam_step.argtypes = [_vp, _pm, _vp, _f, _f, _f, _f, _ci]
+_lib.gw_surrogate_workspace_size.argtypes = [_ps, ctypes.POINTER(_sz)]
+_lib.gw_surrogate_features.argtypes = [_vp, _ps, _vp, _vp, _sz]
+_lib.gw_surrogate_targets.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp, _vp]
+_lib.gw_surrogate_apply.argtypes = [_vp, _ci, _ci, _vp, _ci, _vp]
+_lib.gw_surrogate_judge.argtypes = [_vp, _ps, _vp, _ci, _vp, _ci, ctypes.POINTER(_ci), ctypes.POINTER(_ci), _vp, _vp,
+                                    _sz]
+
 _lib.gw_profile_enable.argtypes = [_ci]
 _lib.gw_profile_reset.argtypes = []
 _lib.gw_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(_ci), ctypes.POINTER(ctypes.c_double)]
 
 EXPORTED = ("gw_last_error", "gw_version", "gw_project_workspace_size", "gw_project",
             "gw_polarization_workspace_size", "gw_polarization", "gw_screen_workspace_size", "gw_screen",
-            "gw_profile_enable", "gw_profile_reset", "gw_profile_query")
+            "gw_profile_enable", "gw_profile_reset", "gw_profile_query",
+            "gw_mlp_sizes", "gw_mlp_sync_bf16", "gw_mlp_forward", "gw_mlp_loss", "gw_mlp_workspace_size",
+            "gw_mlp_backward", "gw_mlp_adam_step", "gw_surrogate_workspace_size", "gw_surrogate_features",
+            "gw_surrogate_targets", "gw_surrogate_apply", "gw_surrogate_judge")
 
 
 def lib():
@@ -276,3 +309,159 @@ def gw_profile_query(kernel: str):
     ms = ctypes.c_double(0.0)
     _check(_lib.gw_profile_query(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+# ------------------------------------------------------------------ perceptron
+
+def gw_mlp_sizes(n_in: int, width: int, n_out: int):
+    a, b = _sz(0), _sz(0)
+    _check(_lib.gw_mlp_sizes(n_in, width, n_out, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+class Mlp:
+    """Device-resident parameters of the 3-layer perceptron (see gw.h)."""
+
+    def __init__(self, n_in: int, width: int, n_out: int, device, master: Optional[np.ndarray] = None,
+                 train: bool = True):
+        self.n_in, self.width, self.n_out = n_in, width, n_out
+        n_p, n_b = gw_mlp_sizes(n_in, width, n_out)
+        self.device = torch.device(device)
+        self.master = torch.zeros(n_p, dtype=torch.float32, device=self.device)
+        if master is not None:
+            if master.size != n_p:
+                raise ValueError(f"master has {master.size} values, expected {n_p}")
+            self.master.copy_(torch.from_numpy(np.ascontiguousarray(master, dtype=np.float32)))
+        self.adam_m = torch.zeros_like(self.master) if train else None
+        self.adam_v = torch.zeros_like(self.master) if train else None
+        self.wt = torch.zeros(n_b, dtype=torch.int16, device=self.device)
+        self.wk = torch.zeros(n_b, dtype=torch.int16, device=self.device)
+        self.step = 0
+        self.desc = GwMlp(n_in, width, n_out, self.master.data_ptr(),
+                          self.adam_m.data_ptr() if train else None, self.adam_v.data_ptr() if train else None,
+                          self.wt.data_ptr(), self.wk.data_ptr())
+        self.sync()
+
+    @staticmethod
+    def flat_from_dict(p: dict, n_in: int, width: int, n_out: int) -> np.ndarray:
+        """Master layout from {W1,b1,W2,b2,W3,b3} (zero-padded to the layer sizes)."""
+        def pad(a, shape):
+            out = np.zeros(shape)
+            a = np.asarray(a)
+            out[tuple(slice(0, s) for s in a.shape)] = a
+            return out
+        parts = [pad(p["W1"], (n_in, width)), pad(p["b1"], (width,)), pad(p["W2"], (width, width)),
+                 pad(p["b2"], (width,)), pad(p["W3"], (width, n_out)), pad(p["b3"], (n_out,))]
+        return np.concatenate([x.reshape(-1) for x in parts]).astype(np.float32)
+
+    def to_dict(self) -> dict:
+        m = self.master.cpu().numpy().astype(np.float64)
+        a, w, o = self.n_in, self.width, self.n_out
+        offs = np.cumsum([0, a * w, w, w * w, w, w * o, o])
+        return {"W1": m[offs[0]:offs[1]].reshape(a, w), "b1": m[offs[1]:offs[2]],
+                "W2": m[offs[2]:offs[3]].reshape(w, w), "b2": m[offs[3]:offs[4]],
+                "W3": m[offs[4]:offs[5]].reshape(w, o), "b3": m[offs[5]:offs[6]]}
+
+    def sync(self, stream=None):
+        _check(_lib.gw_mlp_sync_bf16(_stream(stream), ctypes.byref(self.desc)))
+
+    def forward(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None, act: Optional[torch.Tensor] = None,
+                stream=None):
+        _dev_tensor(X, "X", torch.float32)
+        rows = X.shape[0]
+        if Y is None:
+            Y = torch.empty((rows, self.n_out), dtype=torch.float32, device=X.device)
+        if act is None:
+            act = torch.empty((rows, 4 * self.width), dtype=torch.float32, device=X.device)
+        _check(_lib.gw_mlp_forward(_stream(stream), ctypes.byref(self.desc), X.data_ptr(), rows, Y.data_ptr(),
+                                   act.data_ptr()))
+        return Y, act
+
+    def loss(self, Y, T, mask=None, n_used: int = 1, stream=None):
+        rows = Y.shape[0]
+        dY = torch.empty_like(Y)
+        L = torch.empty(1, dtype=torch.float32, device=Y.device)
+        _check(_lib.gw_mlp_loss(_stream(stream), rows, self.n_out, n_used, Y.data_ptr(), T.data_ptr(),
+                                mask.data_ptr() if mask is not None else None, dY.data_ptr(), L.data_ptr()))
+        return L, dY
+
+    def backward(self, X, act, dY, grad=None, want_dx=False, stream=None):
+        rows = X.shape[0]
+        if grad is None:
+            grad = torch.empty_like(self.master)
+        dX = torch.empty_like(X) if want_dx else None
+        n = _sz(0)
+        _check(_lib.gw_mlp_workspace_size(rows, self.width, ctypes.byref(n)))
+        ws = workspace(n.value, X.device, "mlp")
+        _check(_lib.gw_mlp_backward(_stream(stream), ctypes.byref(self.desc), X.data_ptr(), act.data_ptr(),
+                                    dY.data_ptr(), rows, grad.data_ptr(), dX.data_ptr() if dX is not None else None,
+                                    ws.data_ptr(), ws.numel()))
+        return grad, dX
+
+    def adam(self, grad, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self.step += 1
+        _check(_lib.gw_mlp_adam_step(_stream(stream), ctypes.byref(self.desc), grad.data_ptr(), lr, b1, b2, eps,
+                                     self.step))
+
+
+# ------------------------------------------------------------ surrogate kernels
+
+class SurrogateArgs:
+    """Marshalled gw_surr_desc (keeps the host arrays alive)."""
+
+    def __init__(self, P_ret: torch.Tensor, eps_dev: torch.Tensor, omega, n_occ: int, cut: int, kq=None,
+                 n_in: int = 32):
+        _dev_tensor(P_ret, "P_ret", torch.complex128)
+        _dev_tensor(eps_dev, "eps", torch.float64)
+        self.omega = np.ascontiguousarray(omega, dtype=np.float64)
+        n_k, nb = eps_dev.shape
+        self.kq = None if kq is None else np.ascontiguousarray(kq, dtype=np.int32)
+        d = GwSurrDesc()
+        d.N, d.n_omega = P_ret.shape[1], self.omega.shape[0]
+        d.omega_host = self.omega.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.n_k, d.n_occ, d.n_unocc, d.cut = n_k, n_occ, nb - n_occ, cut
+        d.kq_host = self.kq.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if self.kq is not None else None
+        d.eps, d.P_ret, d.n_in = eps_dev.data_ptr(), P_ret.data_ptr(), n_in
+        self.desc = d
+        self.tensors = (P_ret, eps_dev)
+
+    def workspace(self, device):
+        n = _sz(0)
+        _check(_lib.gw_surrogate_workspace_size(ctypes.byref(self.desc), ctypes.byref(n)))
+        return workspace(n.value, device, "surrogate")
+
+
+def gw_surrogate_features(args: SurrogateArgs, X: Optional[torch.Tensor] = None, stream=None):
+    d = args.desc
+    if X is None:
+        X = torch.empty((d.N * d.n_omega, d.n_in), dtype=torch.float32, device=args.tensors[0].device)
+    ws = args.workspace(X.device)
+    _check(_lib.gw_surrogate_features(_stream(stream), ctypes.byref(d), X.data_ptr(), ws.data_ptr(), ws.numel()))
+    return X
+
+
+def gw_surrogate_targets(P_ret, P_full, stream=None):
+    n_om, N = P_ret.shape[0], P_ret.shape[1]
+    T = torch.empty(n_om * N, dtype=torch.float32, device=P_ret.device)
+    mask = torch.empty_like(T)
+    _check(_lib.gw_surrogate_targets(_stream(stream), N, n_om, P_ret.data_ptr(), P_full.data_ptr(), T.data_ptr(),
+                                     mask.data_ptr()))
+    return T, mask
+
+
+def gw_surrogate_apply(P: torch.Tensor, Y: torch.Tensor, ldy: int, stream=None):
+    _dev_tensor(P, "P", torch.complex128)
+    _check(_lib.gw_surrogate_apply(_stream(stream), P.shape[1], P.shape[0], Y.data_ptr(), ldy, P.data_ptr()))
+    return P
+
+
+def gw_surrogate_judge(args: SurrogateArgs, Y, ldy, P_sample, sample_rows, stream=None):
+    ks = np.ascontiguousarray([r[0] for r in sample_rows], dtype=np.int32)
+    os_ = np.ascontiguousarray([r[1] for r in sample_rows], dtype=np.int32)
+    err = torch.empty(args.desc.n_omega, dtype=torch.float64, device=P_sample.device)
+    ws = args.workspace(P_sample.device)
+    _check(_lib.gw_surrogate_judge(_stream(stream), ctypes.byref(args.desc), Y.data_ptr(), ldy, P_sample.data_ptr(),
+                                   len(sample_rows), ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                   os_.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), err.data_ptr(), ws.data_ptr(),
+                                   ws.numel()))
+    return err

@@ -81,3 +81,19 @@ def test_training_reduces_loss():
         g, _ = mlp.backward(p, cache, dy)
         p, m, v = mlp.adam_step(p, g, m, v, step, lr=3e-3)
     assert L < 0.1 * L0
+
+
+def test_bf16_rounding_known_values():
+    from oracle.precision import round_bf16, split_bf16
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties to even -> 1
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -7 + 2 ** -20, -2.5, 3.0e38, 1e-40],
+                 dtype=np.float32)
+    r = round_bf16(x)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == np.float32(1 + 2 ** -6)
+    assert r[3] == np.float32(1 + 2 ** -7) and r[4] == -2.5
+    # bf16 has 8 significant bits: unit roundoff 2^-8
+    rng = np.random.default_rng(0)
+    y = rng.standard_normal(10000).astype(np.float32) * 10.0 ** rng.uniform(-5, 5, 10000)
+    assert np.all(np.abs(round_bf16(y) - y) <= 2.0 ** -8 * np.abs(y))
+    hi, lo = split_bf16(y)
+    assert np.all(np.abs(y.astype(np.float64) - hi - lo) <= 2.0 ** -16 * np.abs(y))
