@@ -132,8 +132,15 @@ def main() -> int:
         n, tot = gw.gw_profile_query(name)
         kernels[name] = {"launches": n, "total_ms": tot}
     T_pairs = shp.n_k * shp.n_occ * cutoff
-    flops_proj = 8.0 * N * shp.R * T_pairs
-    flops_acc = 4.0 * N * (N + 1) * T_pairs * n_om
+    # pairs actually projected/accumulated in a step: the explicit sum, the
+    # judge's sample of left-out bands and (if the judge failed) the fallback
+    T_run = T_pairs
+    if surrogate is not None:
+        T_run += shp.n_k * 2 * (shp.n_unocc - cutoff)
+        if sur_report.get("used_fallback"):
+            T_run += shp.n_k * shp.n_occ * (shp.n_unocc - cutoff)
+    flops_proj = 8.0 * N * shp.R * T_run
+    flops_acc = 4.0 * N * (N + 1) * T_run * n_om
     flops_screen = 0.5 * N ** 3 * 8.0 * n_om
     per_step = {f"project_{pre}_kernel": flops_proj, f"herk_{pre}_kernel": flops_acc, "update_kernel": flops_screen,
                 "apply_kernel": 0.0}

@@ -258,30 +258,59 @@ int launch_project_f32(hipStream_t s, int N, int R, const float2* U, const float
 
 
 // ===================================================================== split 16-bit
-// x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even);
-// a product is hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation.
-// Complex numbers travel as one dword per word: (re, im) in the low/high half.
+// Every FP32 operand x is carried as two 16-bit words.
+//   BF16: hi = bf16(x), lo = bf16(x - hi); a product is hi*hi + hi*lo + lo*hi
+//         accumulated in one FP32 accumulator.
+//   FP16: x is first scaled by a power of two s (so that max|x s| lies in
+//         [2^13, 2^14), inside FP16's normal range); hi = f16(x s) and
+//         lo = f16((x s - hi) 2^11); hi*hi goes to one accumulator and
+//         hi*lo + lo*hi to a second, combined as (acc + 2^-11 acc2) / (s_a s_b).
+// Rounding is to nearest even in both formats.  Complex numbers travel as one
+// dword per word: (re, im) in the low/high half.
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
-__device__ inline uint32_t bits_of(bf16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+enum Word { W_BF16 = 0, W_F16 = 1 };
 
-__device__ inline void split_bf16(float re, float im, uint32_t& hi, uint32_t& lo) {
-  bf16x2 h = {(__bf16)re, (__bf16)im};
-  float hr = (float)h[0], hm = (float)h[1];
-  bf16x2 l = {(__bf16)(re - hr), (__bf16)(im - hm)};
-  hi = bits_of(h);
-  lo = bits_of(l);
+template <int WORD>
+__device__ inline void split_word(float re, float im, float s, uint32_t& hi, uint32_t& lo) {
+  if constexpr (WORD == W_BF16) {
+    bf16x2 h = {(__bf16)re, (__bf16)im};
+    bf16x2 l = {(__bf16)(re - (float)h[0]), (__bf16)(im - (float)h[1])};
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
+  } else {
+    float a = re * s, b = im * s;
+    halfx2 h = {(_Float16)a, (_Float16)b};
+    halfx2 l = {(_Float16)((a - (float)h[0]) * 2048.f), (_Float16)((b - (float)h[1]) * 2048.f)};
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
+  }
+}
+
+template <int WORD>
+__device__ inline floatx16 mma16(uint4 a, uint4 b, floatx16 c) {
+  if constexpr (WORD == W_BF16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a), __builtin_bit_cast(halfx8, b), c, 0,
+                                                  0, 0);
+}
+
+// power of two s with max*s in [2^13, 2^14) (1 if max is 0 or not finite)
+__device__ inline float pow2_scale(float mx) {
+  if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+  int e;
+  frexpf(mx, &e);  // mx = m 2^e, m in [0.5, 1)
+  return ldexpf(1.f, 14 - e);
 }
 
 constexpr int KS = 16;               // complex k per LDS stage (two MFMA k-steps of 8)
 constexpr int SW = KS + 4;           // dwords per LDS row (padded)
 
-struct Frag {
-  uint4 v;
-};
-
-__device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 // (re, im) -> (re, -im): flips the sign bit of the high half of every dword
 __device__ inline uint4 frag_conj(uint4 v) {
   return make_uint4(v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u);
@@ -297,7 +326,17 @@ struct Lds16 {
   uint32_t blo[BN * SW];
 };
 
-__device__ inline void mma_stage_bf16(const Lds16& L, AccF32& acc, int wm, int wn, int lane) {
+// Device-side scale bookkeeping of the FP16 words (maxima as float bit
+// patterns; non-negative floats order like their bit patterns).
+struct Scales {
+  unsigned u, psi, m;
+  unsigned w[kMaxOmega];
+};
+
+__device__ inline void atomic_max_pos(unsigned* p, float v) { atomicMax(p, __float_as_uint(v)); }
+
+template <int WORD>
+__device__ inline void mma_stage16(const Lds16& L, AccF32& acc, AccF32& acc2, int wm, int wn, int lane) {
   const int l32 = lane & 31, h = lane >> 5;
 #pragma unroll
   for (int s = 0; s < KS / 8; ++s) {
@@ -323,52 +362,84 @@ __device__ inline void mma_stage_bf16(const Lds16& L, AccF32& acc, int wm, int w
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
-        acc.r[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah[rb]), as_bf16x8(brh[cb]), acc.r[rb][cb], 0, 0, 0);
-        acc.i[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah[rb]), as_bf16x8(bih[cb]), acc.i[rb][cb], 0, 0, 0);
+        acc.r[rb][cb] = mma16<WORD>(ah[rb], brh[cb], acc.r[rb][cb]);
+        acc.i[rb][cb] = mma16<WORD>(ah[rb], bih[cb], acc.i[rb][cb]);
+      }
+    AccF32& c2 = (WORD == W_BF16) ? acc : acc2;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        c2.r[rb][cb] = mma16<WORD>(ah[rb], brl[cb], c2.r[rb][cb]);
+        c2.i[rb][cb] = mma16<WORD>(ah[rb], bil[cb], c2.i[rb][cb]);
       }
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
-        acc.r[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah[rb]), as_bf16x8(brl[cb]), acc.r[rb][cb], 0, 0, 0);
-        acc.i[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ah[rb]), as_bf16x8(bil[cb]), acc.i[rb][cb], 0, 0, 0);
-      }
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        acc.r[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(al[rb]), as_bf16x8(brh[cb]), acc.r[rb][cb], 0, 0, 0);
-        acc.i[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(al[rb]), as_bf16x8(bih[cb]), acc.i[rb][cb], 0, 0, 0);
+        c2.r[rb][cb] = mma16<WORD>(al[rb], brh[cb], c2.r[rb][cb]);
+        c2.i[rb][cb] = mma16<WORD>(al[rb], bih[cb], c2.i[rb][cb]);
       }
   }
 }
 
+// max |component| of a c64 array (FP16 scale of U and psi).
+__global__ void maxabs_kernel(const float2* __restrict__ x, size_t n, unsigned* __restrict__ out) {
+  __shared__ float red[256];
+  float m = 0.f;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    float2 v = x[e];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomic_max_pos(out, red[0]);
+}
+
+__global__ void zero_u32_kernel(unsigned* __restrict__ p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 // U (c64 [N][R]) -> hi/lo words [N][Rp], zero beyond R (Rp = R rounded up to KS).
-__global__ void split_u_bf16_kernel(int N, int R, int Rp, const float2* __restrict__ U, uint32_t* __restrict__ hi,
-                                    uint32_t* __restrict__ lo) {
+template <int WORD>
+__global__ void split_u_kernel(int N, int R, int Rp, const float2* __restrict__ U, const Scales* __restrict__ sc,
+                               uint32_t* __restrict__ hi, uint32_t* __restrict__ lo) {
+  const float s = WORD == W_F16 ? pow2_scale(__uint_as_float(sc->u)) : 1.f;
   size_t n = (size_t)N * Rp;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     int i = (int)(e / Rp), r = (int)(e % Rp);
     float2 x = r < R ? U[(size_t)i * R + r] : make_float2(0.f, 0.f);
     uint32_t h, l;
-    split_bf16(x.x, x.y, h, l);
+    split_word<WORD>(x.x, x.y, s, h, l);
     hi[e] = h;
     lo[e] = l;
   }
 }
 
 // Projection with pre-split U and products split while staging.
-__global__ __launch_bounds__(NT, 1) void project_bf16_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
-                                                             const uint32_t* __restrict__ Ul,
-                                                             const float2* __restrict__ po,
-                                                             const float2* __restrict__ pu, int no, int nu,
-                                                             float2* __restrict__ M, long ldm) {
+template <int WORD>
+__global__ __launch_bounds__(NT, 1) void project16_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
+                                                          const uint32_t* __restrict__ Ul,
+                                                          const float2* __restrict__ po,
+                                                          const float2* __restrict__ pu, int no, int nu,
+                                                          float2* __restrict__ M, long ldm, Scales* __restrict__ sc) {
   __shared__ __attribute__((aligned(16))) Lds16 L;
   const int T = no * nu;
   const int t0 = blockIdx.x * BN;
   const int i0 = blockIdx.y * BM;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
+  float sF = 1.f, unscale = 1.f;
+  if constexpr (WORD == W_F16) {
+    const float mp = __uint_as_float(sc->psi);
+    sF = pow2_scale(2.f * mp * mp);
+    unscale = 1.f / (pow2_scale(__uint_as_float(sc->u)) * sF);
+  }
   // A staging: 128 rows x 4 groups of 4 complex; two (row, group) slots per thread
   int arow_l[2], agrp[2];
   const uint32_t* ah_src[2];
@@ -415,8 +486,9 @@ __global__ __launch_bounds__(NT, 1) void project_bf16_kernel(int N, int R, int R
       ru[q] = ok ? urow[q][r] : make_float2(0.f, 0.f);
     }
   };
-  AccF32 acc;
+  AccF32 acc, acc2;
   acc.zero();
+  if constexpr (WORD == W_F16) acc2.zero();
   gload(0);
   for (int r0 = 0; r0 < R; r0 += KS) {
     __syncthreads();
@@ -431,14 +503,15 @@ __global__ __launch_bounds__(NT, 1) void project_bf16_kernel(int N, int R, int R
       float fr = ro[q].x * ru[q].x + ro[q].y * ru[q].y;
       float fi = ro[q].x * ru[q].y - ro[q].y * ru[q].x;
       uint32_t hh, ll;
-      split_bf16(fr, fi, hh, ll);
+      split_word<WORD>(fr, fi, sF, hh, ll);
       L.bhi[row * SW + kq] = hh;
       L.blo[row * SW + kq] = ll;
     }
     __syncthreads();
     if (r0 + KS < R) gload(r0 + KS);
-    mma_stage_bf16(L, acc, wm, wn, lane);
+    mma_stage16<WORD>(L, acc, acc2, wm, wn, lane);
   }
+  float mloc = 0.f;
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -448,14 +521,36 @@ __global__ __launch_bounds__(NT, 1) void project_bf16_kernel(int N, int R, int R
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         int gi = i0 + acc_row(wm, rb, v, lane);
-        if (gi < N) M[(size_t)gi * ldm + gt] = make_float2(acc.r[rb][cb][v], acc.i[rb][cb][v]);
+        if (gi < N) {
+          float re = acc.r[rb][cb][v], im = acc.i[rb][cb][v];
+          if constexpr (WORD == W_F16) {
+            re = (re + acc2.r[rb][cb][v] * (1.f / 2048.f)) * unscale;
+            im = (im + acc2.i[rb][cb][v] * (1.f / 2048.f)) * unscale;
+            mloc = fmaxf(mloc, fmaxf(fabsf(re), fabsf(im)));
+          }
+          M[(size_t)gi * ldm + gt] = make_float2(re, im);
+        }
       }
     }
+  if constexpr (WORD == W_F16) {
+    // block maximum of |M| for the accumulation's scale
+    __shared__ float red[NT];
+    red[tid] = mloc;
+    __syncthreads();
+    for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
+      if (tid < s2) red[tid] = fmaxf(red[tid], red[tid + s2]);
+      __syncthreads();
+    }
+    if (tid == 0 && sc) atomic_max_pos(&sc->m, red[0]);
+  }
 }
 
 // Accumulation with both operands split while staging.
-__global__ __launch_bounds__(NT, 2) void herk_bf16_kernel(int N, int T, const float2* __restrict__ M, long ldm,
-                                                          const float* __restrict__ w, double2* __restrict__ P) {
+template <int WORD>
+__global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void herk16_kernel(int N, int T, const float2* __restrict__ M,
+                                                                            long ldm, const float* __restrict__ w,
+                                                                            double2* __restrict__ P,
+                                                                            const Scales* __restrict__ sc) {
   __shared__ __attribute__((aligned(16))) Lds16 L;
   int bi, bj;
   lower_tile(blockIdx.x, bi, bj);
@@ -464,6 +559,13 @@ __global__ __launch_bounds__(NT, 2) void herk_bf16_kernel(int N, int T, const fl
   const int i0 = bi * BM, j0 = bj * BN;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
+  float sA = 1.f, sB = 1.f, unscale = 1.f;
+  if constexpr (WORD == W_F16) {
+    const float mm = __uint_as_float(sc->m);
+    sA = pow2_scale(mm * __uint_as_float(sc->w[om]));
+    sB = pow2_scale(mm);
+    unscale = 1.f / (sA * sB);
+  }
   const int kq = tid % KS, rq = tid / KS;
   const float2* arow[LOADS];
   const float2* brow[LOADS];
@@ -488,8 +590,9 @@ __global__ __launch_bounds__(NT, 2) void herk_bf16_kernel(int N, int T, const fl
       rb_[q] = (bok[q] && tok) ? brow[q][t] : make_float2(0.f, 0.f);
     }
   };
-  AccF32 acc;
+  AccF32 acc, acc2;
   acc.zero();
+  if constexpr (WORD == W_F16) acc2.zero();
   gload(0);
   for (int t0 = 0; t0 < T; t0 += KS) {
     __syncthreads();
@@ -497,16 +600,16 @@ __global__ __launch_bounds__(NT, 2) void herk_bf16_kernel(int N, int T, const fl
     for (int q = 0; q < LOADS; ++q) {
       int row = rq + 16 * q;
       uint32_t hh, ll;
-      split_bf16(ra[q].x * rw, ra[q].y * rw, hh, ll);
+      split_word<WORD>(ra[q].x * rw, ra[q].y * rw, sA, hh, ll);
       L.ahi[row * SW + kq] = hh;
       L.alo[row * SW + kq] = ll;
-      split_bf16(rb_[q].x, -rb_[q].y, hh, ll);
+      split_word<WORD>(rb_[q].x, -rb_[q].y, sB, hh, ll);
       L.bhi[row * SW + kq] = hh;
       L.blo[row * SW + kq] = ll;
     }
     __syncthreads();
     if (t0 + KS < T) gload(t0 + KS);
-    mma_stage_bf16(L, acc, wm, wn, lane);
+    mma_stage16<WORD>(L, acc, acc2, wm, wn, lane);
   }
   double2* Pj = P + (size_t)om * N * N;
 #pragma unroll
@@ -519,32 +622,95 @@ __global__ __launch_bounds__(NT, 2) void herk_bf16_kernel(int N, int T, const fl
       for (int v = 0; v < 16; ++v) {
         int gi = i0 + acc_row(wm, rb, v, lane);
         if (gi < N) {
+          double re = acc.r[rb][cb][v], im = acc.i[rb][cb][v];
+          if constexpr (WORD == W_F16) {
+            re = (re + (double)acc2.r[rb][cb][v] * (1.0 / 2048.0)) * unscale;
+            im = (im + (double)acc2.i[rb][cb][v] * (1.0 / 2048.0)) * unscale;
+          }
           double2 p = Pj[(size_t)gi * N + gj];
-          p.x += (double)acc.r[rb][cb][v];
-          p.y += (double)acc.i[rb][cb][v];
+          p.x += re;
+          p.y += im;
           Pj[(size_t)gi * N + gj] = p;
         }
       }
     }
 }
 
+// FP16 path: weights as in weights_f32_kernel plus max |w_j| per frequency.
+__global__ void weights_f32_max_kernel(const double* __restrict__ eps, int n_bands, int n_occ, Chunk c, OmegaList om,
+                                       float* __restrict__ w, Scales* __restrict__ sc) {
+  __shared__ float red[256];
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int T = c.no * c.nu;
+  double d = 0.0;
+  if (t < T) {
+    int n = c.n0 + t / c.nu;
+    int u = c.u0 + t % c.nu;
+    d = eps[(size_t)c.k * n_bands + n] - eps[(size_t)c.kq * n_bands + n_occ + u];
+  }
+  for (int j = 0; j < om.n; ++j) {
+    float x = 0.f;
+    if (t < T) {
+      x = (float)(4.0 * d / (d * d + om.w[j] * om.w[j]));
+      w[(size_t)j * T + t] = x;
+    }
+    red[threadIdx.x] = fabsf(x);
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomic_max_pos(&sc->w[j], red[0]);
+    __syncthreads();
+  }
+}
+
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-int launch_split_u_bf16(hipStream_t s, int N, int R, int Rp, const float2* U, uint32_t* hi, uint32_t* lo) {
-  size_t n = (size_t)N * Rp;
-  unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
-  hipLaunchKernelGGL(split_u_bf16_kernel, dim3(blocks), dim3(256), 0, s, N, R, Rp, U, hi, lo);
-  GW_LAUNCHED("split_u_bf16_kernel");
+int launch_zero_u32(hipStream_t s, unsigned* p, int n) {
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  GW_LAUNCHED("zero_u32_kernel");
   return GW_OK;
 }
 
-int launch_project_bf16(hipStream_t s, int N, int R, int Rp, const uint32_t* Uh, const uint32_t* Ul, const float2* po,
-                        const float2* pu, int no, int nu, float2* M, long ldm) {
+int launch_maxabs(hipStream_t s, const float2* x, size_t n, unsigned* out) {
+  unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(maxabs_kernel, dim3(std::max(1u, blocks)), dim3(256), 0, s, x, n, out);
+  GW_LAUNCHED("maxabs_kernel");
+  return GW_OK;
+}
+
+// Split U (and, for FP16, measure max|U| and max|psi| first).
+int prepare_split(hipStream_t s, int word, int N, int R, int Rp, const float2* U, const float2* psi, size_t n_psi,
+                  uint32_t* hi, uint32_t* lo, Scales* sc) {
+  int st;
+  if (word == W_F16) {
+    if ((st = launch_zero_u32(s, reinterpret_cast<unsigned*>(sc), (int)(sizeof(Scales) / 4))) != GW_OK) return st;
+    if ((st = launch_maxabs(s, U, (size_t)N * R, &sc->u)) != GW_OK) return st;
+    if ((st = launch_maxabs(s, psi, n_psi, &sc->psi)) != GW_OK) return st;
+  }
+  size_t n = (size_t)N * Rp;
+  unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+  if (word == W_BF16)
+    hipLaunchKernelGGL(split_u_kernel<W_BF16>, dim3(blocks), dim3(256), 0, s, N, R, Rp, U, sc, hi, lo);
+  else
+    hipLaunchKernelGGL(split_u_kernel<W_F16>, dim3(blocks), dim3(256), 0, s, N, R, Rp, U, sc, hi, lo);
+  GW_LAUNCHED("split_u_kernel");
+  return GW_OK;
+}
+
+int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32_t* Uh, const uint32_t* Ul,
+                     const float2* po, const float2* pu, int no, int nu, float2* M, long ldm, Scales* sc) {
   int T = no * nu;
   dim3 grid((T + BN - 1) / BN, (N + BM - 1) / BM);
-  ProfScope prof(s, "project_bf16_kernel");
-  hipLaunchKernelGGL(project_bf16_kernel, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M, ldm);
-  GW_LAUNCHED("project_bf16_kernel");
+  if (word == W_BF16) {
+    ProfScope prof(s, "project_bf16_kernel");
+    hipLaunchKernelGGL(project16_kernel<W_BF16>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M, ldm, sc);
+  } else {
+    ProfScope prof(s, "project_f16_kernel");
+    hipLaunchKernelGGL(project16_kernel<W_F16>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M, ldm, sc);
+  }
+  GW_LAUNCHED("project16_kernel");
   return GW_OK;
 }
 
@@ -563,7 +729,7 @@ void mfma_adjust_chunk(int, int&, int&, int, int) {}
 static size_t split_u_bytes(int precision, int N, int R) {
   if (precision == GW_FP32) return 0;
   size_t Rp = (size_t)round_up(R, KS);
-  return 2 * align_up((size_t)N * Rp * sizeof(uint32_t));
+  return 2 * align_up((size_t)N * Rp * sizeof(uint32_t)) + align_up(sizeof(Scales));
 }
 
 size_t mfma_pol_workspace(int precision, int N, int R, int tc, int n_omega) {
@@ -577,6 +743,8 @@ size_t mfma_project_workspace(int precision, int N, int R, int n_occ, int n_unoc
   return split_u_bytes(precision, N, R);
 }
 
+static int word_of(int precision) { return precision == GW_SPLIT_FP16 ? W_F16 : W_BF16; }
+
 int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_unocc, const void* U,
                  const void* psi_occ, const void* psi_unocc, void* M, void* ws, size_t ws_bytes) {
   (void)ws_bytes;
@@ -584,29 +752,46 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
     return launch_project_f32(s, N, R, static_cast<const float2*>(U), static_cast<const float2*>(psi_occ),
                               static_cast<const float2*>(psi_unocc), n_occ, n_unocc, static_cast<float2*>(M),
                               (long)n_occ * n_unocc);
-  if (precision != GW_SPLIT_BF16) return fail(GW_ERR_UNSUPPORTED, "gw_project: precision not built yet");
+  const int word = word_of(precision);
   const int Rp = round_up(R, KS);
   Carver cv(ws);
   uint32_t* Uh = cv.take<uint32_t>((size_t)N * Rp);
   uint32_t* Ul = cv.take<uint32_t>((size_t)N * Rp);
-  int st = launch_split_u_bf16(s, N, R, Rp, static_cast<const float2*>(U), Uh, Ul);
-  if (st != GW_OK) return st;
-  return launch_project_bf16(s, N, R, Rp, Uh, Ul, static_cast<const float2*>(psi_occ),
-                             static_cast<const float2*>(psi_unocc), n_occ, n_unocc, static_cast<float2*>(M),
-                             (long)n_occ * n_unocc);
+  Scales* sc = cv.take<Scales>(1);
+  int st;
+  if (word == W_F16) {
+    // psi_occ and psi_unocc are separate arrays: take the larger of their maxima
+    if ((st = launch_zero_u32(s, reinterpret_cast<unsigned*>(sc), (int)(sizeof(Scales) / 4))) != GW_OK) return st;
+    if ((st = launch_maxabs(s, static_cast<const float2*>(psi_occ), (size_t)n_occ * R, &sc->psi)) != GW_OK) return st;
+    if ((st = launch_maxabs(s, static_cast<const float2*>(psi_unocc), (size_t)n_unocc * R, &sc->psi)) != GW_OK)
+      return st;
+    if ((st = launch_maxabs(s, static_cast<const float2*>(U), (size_t)N * R, &sc->u)) != GW_OK) return st;
+    size_t n = (size_t)N * Rp;
+    unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(split_u_kernel<W_F16>, dim3(blocks), dim3(256), 0, s, N, R, Rp,
+                       static_cast<const float2*>(U), sc, Uh, Ul);
+    GW_LAUNCHED("split_u_kernel");
+  } else if ((st = prepare_split(s, word, N, R, Rp, static_cast<const float2*>(U), nullptr, 0, Uh, Ul, sc)) != GW_OK) {
+    return st;
+  }
+  return launch_project16(s, word, N, R, Rp, Uh, Ul, static_cast<const float2*>(psi_occ),
+                          static_cast<const float2*>(psi_unocc), n_occ, n_unocc, static_cast<float2*>(M),
+                          (long)n_occ * n_unocc, sc);
 }
 
 int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
                       const OmegaList& om, void* ws) {
-  if (d.precision != GW_FP32 && d.precision != GW_SPLIT_BF16)
-    return fail(GW_ERR_UNSUPPORTED, "gw_polarization: precision not built yet");
   Carver cv(ws);
   const int Rp = round_up(d.R, KS);
   uint32_t* Uh = nullptr;
   uint32_t* Ul = nullptr;
-  if (d.precision == GW_SPLIT_BF16) {
+  Scales* sc = nullptr;
+  const bool split = d.precision != GW_FP32;
+  const int word = word_of(d.precision);
+  if (split) {
     Uh = cv.take<uint32_t>((size_t)d.N * Rp);
     Ul = cv.take<uint32_t>((size_t)d.N * Rp);
+    sc = cv.take<Scales>(1);
   }
   float2* M = cv.take<float2>((size_t)d.N * tc);
   float* w = cv.take<float>((size_t)d.n_omega * tc);
@@ -615,29 +800,39 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
   const int nb = d.n_occ + d.n_unocc;
   const int ntile = (d.N + BM - 1) / BM;
   double2* P = reinterpret_cast<double2*>(d.P);
-  if (d.precision == GW_SPLIT_BF16) {
-    int st = launch_split_u_bf16(s, d.N, d.R, Rp, U, Uh, Ul);
-    if (st != GW_OK) return st;
-  }
+  int st;
+  if (split && (st = prepare_split(s, word, d.N, d.R, Rp, U, psi, (size_t)d.n_k * nb * d.R, Uh, Ul, sc)) != GW_OK)
+    return st;
   for (const Chunk& c : chunks) {
     const int T = c.pairs();
-    hipLaunchKernelGGL(weights_f32_kernel, dim3((T + 255) / 256), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om, w);
-    GW_LAUNCHED("weights_f32_kernel");
+    if (word == W_F16 && split) {
+      // per-chunk maxima of |M| and |w_j|
+      if ((st = launch_zero_u32(s, &sc->m, 1 + kMaxOmega)) != GW_OK) return st;
+      hipLaunchKernelGGL(weights_f32_max_kernel, dim3((T + 255) / 256), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om,
+                         w, sc);
+      GW_LAUNCHED("weights_f32_max_kernel");
+    } else {
+      hipLaunchKernelGGL(weights_f32_kernel, dim3((T + 255) / 256), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om, w);
+      GW_LAUNCHED("weights_f32_kernel");
+    }
     const float2* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
     const float2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
     dim3 hgrid(ntile * (ntile + 1) / 2, d.n_omega);
-    if (d.precision == GW_FP32) {
-      int st = launch_project_f32(s, d.N, d.R, U, po, pu, c.no, c.nu, M, T);
-      if (st != GW_OK) return st;
+    if (!split) {
+      if ((st = launch_project_f32(s, d.N, d.R, U, po, pu, c.no, c.nu, M, T)) != GW_OK) return st;
       ProfScope prof(s, "herk_f32_kernel");
       hipLaunchKernelGGL(herk_f32_kernel, hgrid, dim3(NT), 0, s, d.N, T, M, (long)T, w, P);
       GW_LAUNCHED("herk_f32_kernel");
-    } else {
-      int st = launch_project_bf16(s, d.N, d.R, Rp, Uh, Ul, po, pu, c.no, c.nu, M, T);
-      if (st != GW_OK) return st;
+    } else if (word == W_BF16) {
+      if ((st = launch_project16(s, word, d.N, d.R, Rp, Uh, Ul, po, pu, c.no, c.nu, M, T, sc)) != GW_OK) return st;
       ProfScope prof(s, "herk_bf16_kernel");
-      hipLaunchKernelGGL(herk_bf16_kernel, hgrid, dim3(NT), 0, s, d.N, T, M, (long)T, w, P);
+      hipLaunchKernelGGL(herk16_kernel<W_BF16>, hgrid, dim3(NT), 0, s, d.N, T, M, (long)T, w, P, sc);
       GW_LAUNCHED("herk_bf16_kernel");
+    } else {
+      if ((st = launch_project16(s, word, d.N, d.R, Rp, Uh, Ul, po, pu, c.no, c.nu, M, T, sc)) != GW_OK) return st;
+      ProfScope prof(s, "herk_f16_kernel");
+      hipLaunchKernelGGL(herk16_kernel<W_F16>, hgrid, dim3(NT), 0, s, d.N, T, M, (long)T, w, P, sc);
+      GW_LAUNCHED("herk_f16_kernel");
     }
   }
   return GW_OK;
