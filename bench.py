@@ -50,11 +50,92 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for cpu_baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for HBM traffic counters)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv outputs (bench run, then the copy "
+                         "calibration) into the traffic file")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c5.json"),
+                    help="measured per-launch HBM traffic of the dominant kernel (from rocprofv3 --pmc)")
     return ap.parse_args()
+
+
+def copy_calibration() -> int:
+    """A plain copy of 2^30 bytes: its FETCH_SIZE / WRITE_SIZE counters give
+    the factor between the counter readings and bytes moved."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}))
+    return 0
+
+
+def _pmc_means(d: str, counter: str) -> dict:
+    """mean counter value per dispatch, by kernel name, from rocprofv3 csv output"""
+    import csv
+    import glob
+    acc = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = row.get("Kernel_Name", "")
+                key = name.split("(")[0].replace("gw::(anonymous namespace)::", "")
+                for pre in ("gw::(anonymous namespace)::", "void "):
+                    if key.startswith(pre):
+                        key = key[len(pre):]
+                acc.setdefault(key, []).append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def summarize_pmc(a) -> int:
+    fd, wd, cfd, cwd = a.summarize_pmc
+    fetch, write = _pmc_means(fd, "FETCH_SIZE"), _pmc_means(wd, "WRITE_SIZE")
+    cf, cw = _pmc_means(cfd, "FETCH_SIZE"), _pmc_means(cwd, "WRITE_SIZE")
+    copy_f = max(cf.values()) if cf else None
+    copy_w = max(cw.values()) if cw else None
+    n = 1 << 30
+    kf = n / (copy_f * 1024.0) if copy_f else None   # bytes per reported KiB
+    kw = n / (copy_w * 1024.0) if copy_w else None
+    out = {"workload": a.workload, "source_hash": kernel_source_hash(), "copy_factor_fetch": kf,
+           "copy_factor_write": kw, "kernels": {}}
+    for k in sorted(set(fetch) | set(write)):
+        fb = fetch.get(k, 0.0) * 1024.0 * (kf or 1.0)
+        wb = write.get(k, 0.0) * 1024.0 * (kw or 1.0)
+        out["kernels"][k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
+    dom = "project_bf16v2_kernel" if "project_bf16v2_kernel" in out["kernels"] else None
+    if dom:
+        out["kernel"] = "project_bf16_kernel"
+        out["bytes_per_launch"] = out["kernels"][dom]["fetch_bytes_per_launch"] + \
+            out["kernels"][dom]["write_bytes_per_launch"]
+    with open(a.traffic, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+    return 0
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_mfma.hip",):
+        with open(os.path.join(ROOT, "paper_1003_0316_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def main() -> int:
     a = parse()
+    if a.copy_calibration:
+        return copy_calibration()
+    if a.summarize_pmc:
+        return summarize_pmc(a)
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build runs on one GPU only "
               f"(the k-point / occupied-band shards and the reduce-scatter of P over frequencies are "
@@ -150,8 +231,16 @@ def main() -> int:
     alg_per_launch = per_step[dom] * a.steps / max(1, dk["launches"])
     achieved = alg_per_launch / (avg_ms * 1e-3) / 1e12
     peak_dtype = "fp64" if dom == "update_kernel" else ("bf16" if pre == "bf16" else ("fp16" if pre == "f16" else "fp32"))
+    traffic = None
+    try:
+        with open(a.traffic) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel") == dom and tr.get("source_hash") == kernel_source_hash() and tr.get("workload") == a.workload:
+            traffic = tr["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[peak_dtype],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[peak_dtype], 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[peak_dtype], 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4), "alg_flops_per_launch": alg_per_launch,
                 "launches": dk["launches"]}
     breakdown = {k: round(v["total_ms"] / a.steps / 1e3, 4) for k, v in kernels.items()}

@@ -665,6 +665,272 @@ __global__ void weights_f32_max_kernel(const double* __restrict__ eps, int n_ban
   }
 }
 
+// ------------------------------------------------------------ large-tile BF16
+// 256 x 128 output tiles: 4 waves in a 2 x 2 arrangement, each owning 128 x 64
+// complex outputs (4 x 2 blocks of 32 x 32, 256 FP32 accumulators per lane),
+// LDS double-buffered so one barrier separates consecutive K stages.
+constexpr int BM2 = 256, BN2 = 128;
+
+struct Acc2 {
+  floatx16 r[4][2];
+  floatx16 i[4][2];
+  __device__ void zero() {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          r[a][b][v] = 0.f;
+          i[a][b][v] = 0.f;
+        }
+  }
+};
+
+struct Lds2 {
+  uint32_t ahi[BM2 * SW];
+  uint32_t alo[BM2 * SW];
+  uint32_t bhi[BN2 * SW];
+  uint32_t blo[BN2 * SW];
+};
+
+__device__ inline void mma_stage_v2(const Lds2& L, Acc2& acc, int wm, int wn, int lane) {
+  const int l32 = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int s = 0; s < KS / 8; ++s) {
+    const int off = s * 8 + h * 4;
+    uint4 brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      int col = wn * 64 + cb * 32 + l32;
+      uint4 bh = *reinterpret_cast<const uint4*>(&L.bhi[col * SW + off]);
+      uint4 bl = *reinterpret_cast<const uint4*>(&L.blo[col * SW + off]);
+      brh[cb] = frag_conj(bh);
+      brl[cb] = frag_conj(bl);
+      bih[cb] = frag_swap(bh);
+      bil[cb] = frag_swap(bl);
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      int row = wm * 128 + rb * 32 + l32;
+      uint4 ah = *reinterpret_cast<const uint4*>(&L.ahi[row * SW + off]);
+      uint4 al = *reinterpret_cast<const uint4*>(&L.alo[row * SW + off]);
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        acc.r[rb][cb] = mma16<W_BF16>(ah, brh[cb], acc.r[rb][cb]);
+        acc.i[rb][cb] = mma16<W_BF16>(ah, bih[cb], acc.i[rb][cb]);
+        acc.r[rb][cb] = mma16<W_BF16>(ah, brl[cb], acc.r[rb][cb]);
+        acc.i[rb][cb] = mma16<W_BF16>(ah, bil[cb], acc.i[rb][cb]);
+        acc.r[rb][cb] = mma16<W_BF16>(al, brh[cb], acc.r[rb][cb]);
+        acc.i[rb][cb] = mma16<W_BF16>(al, bih[cb], acc.i[rb][cb]);
+      }
+    }
+  }
+}
+
+__device__ inline int acc2_row(int wm, int rb, int v, int lane) {
+  return wm * 128 + rb * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+}
+
+// Projection, BF16 words, 256 x 128 tiles.
+__global__ __launch_bounds__(NT, 1) void project_bf16v2_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
+                                                               const uint32_t* __restrict__ Ul,
+                                                               const float2* __restrict__ po,
+                                                               const float2* __restrict__ pu, int no, int nu,
+                                                               float2* __restrict__ M, long ldm) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  Lds2* Lb = reinterpret_cast<Lds2*>(lds_raw);
+  const int T = no * nu;
+  const int t0 = blockIdx.x * BN2;
+  const int i0 = blockIdx.y * BM2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  // A staging: 256 rows x 4 groups of 4 complex -> 4 (row, group) slots per thread
+  int aoff[4];
+  bool aok[4];
+  size_t asrc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + q * NT;
+    int row = e >> 2, grp = e & 3;
+    aoff[q] = row * SW + grp * 4;
+    int gi = i0 + row;
+    aok[q] = gi < N;
+    asrc[q] = (size_t)(aok[q] ? gi : 0) * Rp + grp * 4;
+  }
+  // B staging: pair rq + 16 q (q < 8), complex k kq
+  const int kq = tid % KS, rq = tid / KS;
+  size_t ooff[LOADS], uoff[LOADS];
+  bool bok[LOADS];
+#pragma unroll
+  for (int q = 0; q < LOADS; ++q) {
+    int gt = t0 + rq + 16 * q;
+    bok[q] = gt < T;
+    int t = bok[q] ? gt : 0;
+    ooff[q] = (size_t)(t / nu) * R;
+    uoff[q] = (size_t)(t % nu) * R;
+  }
+  uint4 rah[4], ral[4];
+  float2 ro[LOADS], ru[LOADS];
+  auto gload = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      rah[q] = aok[q] ? *reinterpret_cast<const uint4*>(Uh + asrc[q] + r0) : make_uint4(0, 0, 0, 0);
+      ral[q] = aok[q] ? *reinterpret_cast<const uint4*>(Ul + asrc[q] + r0) : make_uint4(0, 0, 0, 0);
+    }
+    int r = r0 + kq;
+    bool rok = r < R;
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      bool ok = bok[q] && rok;
+      ro[q] = ok ? po[ooff[q] + r] : make_float2(0.f, 0.f);
+      ru[q] = ok ? pu[uoff[q] + r] : make_float2(0.f, 0.f);
+    }
+  };
+  auto lstore = [&](Lds2& L) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<uint4*>(&L.ahi[aoff[q]]) = rah[q];
+      *reinterpret_cast<uint4*>(&L.alo[aoff[q]]) = ral[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      int row = rq + 16 * q;
+      float fr = ro[q].x * ru[q].x + ro[q].y * ru[q].y;
+      float fi = ro[q].x * ru[q].y - ro[q].y * ru[q].x;
+      uint32_t hh, ll;
+      split_word<W_BF16>(fr, fi, 1.f, hh, ll);
+      L.bhi[row * SW + kq] = hh;
+      L.blo[row * SW + kq] = ll;
+    }
+  };
+  Acc2 acc;
+  acc.zero();
+  gload(0);
+  lstore(Lb[0]);
+  __syncthreads();
+  int buf = 0;
+  for (int r0 = 0; r0 < R; r0 += KS) {
+    const bool more = r0 + KS < R;
+    if (more) gload(r0 + KS);
+    mma_stage_v2(Lb[buf], acc, wm, wn, lane);
+    if (more) lstore(Lb[buf ^ 1]);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      int gt = t0 + acc_col(wn, cb, lane);
+      if (gt >= T) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int gi = i0 + acc2_row(wm, rb, v, lane);
+        if (gi < N) M[(size_t)gi * ldm + gt] = make_float2(acc.r[rb][cb][v], acc.i[rb][cb][v]);
+      }
+    }
+}
+
+// tile l of the lower part for 256 x 128 tiles: row block bi owns column blocks 0 .. 2 bi + 1
+__device__ inline void lower_tile_2(int l, int& bi, int& bj) {
+  int b = (int)((sqrt(4.0 * (double)l + 1.0) - 1.0) * 0.5);
+  while ((b + 1) * (b + 2) <= l) ++b;
+  while (b * (b + 1) > l) --b;
+  bi = b;
+  bj = l - b * (b + 1);
+}
+
+// Accumulation, BF16 words, 256 x 128 tiles (rows I, columns J).
+__global__ __launch_bounds__(NT, 1) void herk_bf16v2_kernel(int N, int T, const float2* __restrict__ M, long ldm,
+                                                            const float* __restrict__ w, double2* __restrict__ P) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  Lds2* Lb = reinterpret_cast<Lds2*>(lds_raw);
+  int bi, bj;
+  lower_tile_2(blockIdx.x, bi, bj);
+  const int i0 = bi * BM2, j0 = bj * BN2;
+  if (j0 >= N) return;
+  const int om = blockIdx.y;
+  const float* wj = w + (size_t)om * T;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int kq = tid % KS, rq = tid / KS;
+  // A rows rq + 16 q (q < 16), B rows rq + 16 q (q < 8)
+  size_t aoff[16], boff[LOADS];
+  bool aok[16], bok[LOADS];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    int gi = i0 + rq + 16 * q;
+    aok[q] = gi < N;
+    aoff[q] = (size_t)(aok[q] ? gi : 0) * ldm;
+  }
+#pragma unroll
+  for (int q = 0; q < LOADS; ++q) {
+    int gj = j0 + rq + 16 * q;
+    bok[q] = gj < N;
+    boff[q] = (size_t)(bok[q] ? gj : 0) * ldm;
+  }
+  float2 ra[16], rb_[LOADS];
+  float rw;
+  auto gload = [&](int t0) {
+    int t = t0 + kq;
+    bool tok = t < T;
+    rw = tok ? wj[t] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ra[q] = (aok[q] && tok) ? M[aoff[q] + t] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) rb_[q] = (bok[q] && tok) ? M[boff[q] + t] : make_float2(0.f, 0.f);
+  };
+  auto lstore = [&](Lds2& L) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      uint32_t hh, ll;
+      split_word<W_BF16>(ra[q].x * rw, ra[q].y * rw, 1.f, hh, ll);
+      L.ahi[(rq + 16 * q) * SW + kq] = hh;
+      L.alo[(rq + 16 * q) * SW + kq] = ll;
+    }
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      uint32_t hh, ll;
+      split_word<W_BF16>(rb_[q].x, -rb_[q].y, 1.f, hh, ll);
+      L.bhi[(rq + 16 * q) * SW + kq] = hh;
+      L.blo[(rq + 16 * q) * SW + kq] = ll;
+    }
+  };
+  Acc2 acc;
+  acc.zero();
+  gload(0);
+  lstore(Lb[0]);
+  __syncthreads();
+  int buf = 0;
+  for (int t0 = 0; t0 < T; t0 += KS) {
+    const bool more = t0 + KS < T;
+    if (more) gload(t0 + KS);
+    mma_stage_v2(Lb[buf], acc, wm, wn, lane);
+    if (more) lstore(Lb[buf ^ 1]);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double2* Pj = P + (size_t)om * N * N;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      int gj = j0 + acc_col(wn, cb, lane);
+      if (gj >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int gi = i0 + acc2_row(wm, rb, v, lane);
+        if (gi < N) {
+          double2 p = Pj[(size_t)gi * N + gj];
+          p.x += (double)acc.r[rb][cb][v];
+          p.y += (double)acc.i[rb][cb][v];
+          Pj[(size_t)gi * N + gj] = p;
+        }
+      }
+    }
+}
+
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 int launch_zero_u32(hipStream_t s, unsigned* p, int n) {
@@ -699,9 +965,58 @@ int prepare_split(hipStream_t s, int word, int N, int R, int Rp, const float2* U
   return GW_OK;
 }
 
+// Large tiles pay off once the basis spans a few of them.
+constexpr int kLargeTileN = 256;
+constexpr size_t kLds2Bytes = 2 * sizeof(Lds2);
+
+int enable_large_lds() {
+  static int done = 0;
+  if (done) return GW_OK;
+  GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&project_bf16v2_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds2Bytes));
+  GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&herk_bf16v2_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds2Bytes));
+  done = 1;
+  return GW_OK;
+}
+
+int launch_herk16(hipStream_t s, int word, int N, int T, const float2* M, long ldm, const float* w, int n_omega,
+                  double2* P, const Scales* sc) {
+  if (word == W_BF16 && N >= kLargeTileN) {
+    int st = enable_large_lds();
+    if (st != GW_OK) return st;
+    int nb = (N + BM2 - 1) / BM2;
+    ProfScope prof(s, "herk_bf16_kernel");
+    hipLaunchKernelGGL(herk_bf16v2_kernel, dim3(nb * (nb + 1), n_omega), dim3(NT), kLds2Bytes, s, N, T, M, ldm, w, P);
+    GW_LAUNCHED("herk_bf16v2_kernel");
+    return GW_OK;
+  }
+  const int ntile = (N + BM - 1) / BM;
+  dim3 hgrid(ntile * (ntile + 1) / 2, n_omega);
+  if (word == W_BF16) {
+    ProfScope prof(s, "herk_bf16_kernel");
+    hipLaunchKernelGGL(herk16_kernel<W_BF16>, hgrid, dim3(NT), 0, s, N, T, M, ldm, w, P, sc);
+  } else {
+    ProfScope prof(s, "herk_f16_kernel");
+    hipLaunchKernelGGL(herk16_kernel<W_F16>, hgrid, dim3(NT), 0, s, N, T, M, ldm, w, P, sc);
+  }
+  GW_LAUNCHED("herk16_kernel");
+  return GW_OK;
+}
+
 int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32_t* Uh, const uint32_t* Ul,
                      const float2* po, const float2* pu, int no, int nu, float2* M, long ldm, Scales* sc) {
   int T = no * nu;
+  if (word == W_BF16 && N >= kLargeTileN) {
+    int st = enable_large_lds();
+    if (st != GW_OK) return st;
+    dim3 grid2((T + BN2 - 1) / BN2, (N + BM2 - 1) / BM2);
+    ProfScope prof(s, "project_bf16_kernel");
+    hipLaunchKernelGGL(project_bf16v2_kernel, grid2, dim3(NT), kLds2Bytes, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M,
+                       ldm);
+    GW_LAUNCHED("project_bf16v2_kernel");
+    return GW_OK;
+  }
   dim3 grid((T + BN - 1) / BN, (N + BM - 1) / BM);
   if (word == W_BF16) {
     ProfScope prof(s, "project_bf16_kernel");
@@ -823,16 +1138,9 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
       ProfScope prof(s, "herk_f32_kernel");
       hipLaunchKernelGGL(herk_f32_kernel, hgrid, dim3(NT), 0, s, d.N, T, M, (long)T, w, P);
       GW_LAUNCHED("herk_f32_kernel");
-    } else if (word == W_BF16) {
-      if ((st = launch_project16(s, word, d.N, d.R, Rp, Uh, Ul, po, pu, c.no, c.nu, M, T, sc)) != GW_OK) return st;
-      ProfScope prof(s, "herk_bf16_kernel");
-      hipLaunchKernelGGL(herk16_kernel<W_BF16>, hgrid, dim3(NT), 0, s, d.N, T, M, (long)T, w, P, sc);
-      GW_LAUNCHED("herk_bf16_kernel");
     } else {
       if ((st = launch_project16(s, word, d.N, d.R, Rp, Uh, Ul, po, pu, c.no, c.nu, M, T, sc)) != GW_OK) return st;
-      ProfScope prof(s, "herk_f16_kernel");
-      hipLaunchKernelGGL(herk16_kernel<W_F16>, hgrid, dim3(NT), 0, s, d.N, T, M, (long)T, w, P, sc);
-      GW_LAUNCHED("herk_f16_kernel");
+      if ((st = launch_herk16(s, word, d.N, T, M, (long)T, w, d.n_omega, P, sc)) != GW_OK) return st;
     }
   }
   return GW_OK;

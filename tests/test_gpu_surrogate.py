@@ -205,3 +205,48 @@ def test_surrogate_path_parity_with_trained_model(lib, surr_case):
     ref = osg.apply(Pr, y)
     err = orc.rel_fro(Pd.cpu().numpy(), ref)
     assert err.max() < 1e-4, err
+
+
+def test_surrogate_gain_over_truncation(lib):
+    """On held-out seeds (not used in training) the corrected P is closer to
+    the full-band P than the truncated sum, at every frequency.  The model
+    error itself has no closed form to pin; this measures it against the
+    explicit full-band sum."""
+    import torch
+    from paper_1003_0316_amd.surrogate import DEFAULT_MODEL, Surrogate
+    from paper_1003_0316_amd import train_surrogate as ts
+    if not os.path.exists(DEFAULT_MODEL):
+        pytest.skip("no trained model committed yet")
+    sur = Surrogate.load_default(torch.device("cuda"))
+    seeds = [gwsynth.BASE_SEED + ts.SEED0 + 210, gwsynth.BASE_SEED + ts.SEED0 + 219]
+    ev = ts.evaluate(sur, seeds, torch.device("cuda"), cuts=(300,))
+    r = ev["300"]
+    print("held-out: truncation", r["trunc_per_omega_mean"], "corrected", r["model_per_omega_mean"])
+    assert np.all(np.array(r["model_per_omega_mean"]) < np.array(r["trunc_per_omega_mean"]))
+    assert r["model_mean"] < 0.5 * r["trunc_mean"]
+
+
+def test_surrogate_judge_forces_fallback(lib):
+    """judge_tol = 0 always fails the judge: the path must return the explicit
+    full-band sum (host-forced condition)."""
+    import torch
+    from paper_1003_0316_amd.surrogate import DEFAULT_MODEL, Surrogate
+    if not os.path.exists(DEFAULT_MODEL):
+        pytest.skip("no trained model committed yet")
+    shp = gwsynth.make_shape(n_k=2, n_b=80, R=512, N=150, n_occ=3, n_unocc=60)
+    inp = gwsynth.generate(shp, seed=29, omega=gwsynth.omega_mesh("m16"))
+    dev = torch.device("cuda")
+    U = torch.from_numpy(inp.U).to(dev, torch.complex64)
+    psi = torch.from_numpy(inp.psi).to(dev, torch.complex64)
+    eps = torch.from_numpy(inp.eps).to(dev)
+    sur = Surrogate.load_default(dev, judge_tol=0.0)
+    pol = lib.PolarizationCall(U, psi, inp.eps, inp.omega, 3, precision="split_bf16", eps_dev=eps, kq=inp.kq,
+                               unocc_range=(0, 20))
+    ws = torch.empty(pol.workspace_size(), dtype=torch.uint8, device=dev)
+    P, rep = sur.run(pol, ws, U, psi, inp.eps, eps, inp.omega, 3, 20, inp.kq)
+    torch.cuda.synchronize()
+    assert rep["used_fallback"]
+    Ur = inp.U.astype(np.complex64).astype(np.complex128)
+    pr = inp.psi.astype(np.complex64).astype(np.complex128)
+    ref = orc.polarization(Ur, pr, inp.eps, inp.omega, 3, kq=inp.kq)
+    assert orc.rel_fro(P.cpu().numpy(), ref).max() < 1e-4
