@@ -15,6 +15,7 @@
 #include "gw_mfma.hpp"
 
 #include <algorithm>
+#include <string>
 
 namespace gw {
 namespace {
@@ -832,6 +833,161 @@ __global__ __launch_bounds__(NT, 1) void project_bf16v2_kernel(int N, int R, int
     }
 }
 
+// Projection, BF16 words, 256 x 128 tiles, software-pipelined: the staging of
+// stage s+1 (product, hi/lo split, LDS stores) is spread between the MFMA
+// groups of stage s so that it issues in the shadow of the matrix cores, and
+// global loads run one full stage ahead.  Loads are branch-free (addresses
+// clamped inside the arrays, values zeroed by selects).
+__global__ __launch_bounds__(NT, 1) void project_bf16v3_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
+                                                               const uint32_t* __restrict__ Ul,
+                                                               const float2* __restrict__ po,
+                                                               const float2* __restrict__ pu, int no, int nu,
+                                                               float2* __restrict__ M, long ldm) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  Lds2* Lb = reinterpret_cast<Lds2*>(lds_raw);
+  const int T = no * nu;
+  const int t0 = blockIdx.x * BN2;
+  const int i0 = blockIdx.y * BM2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int l32 = lane & 31, h = lane >> 5;
+  int aoff[4];
+  uint32_t amask[4];
+  size_t asrc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + q * NT;
+    int row = e >> 2, grp = e & 3;
+    aoff[q] = row * SW + grp * 4;
+    int gi = i0 + row;
+    amask[q] = gi < N ? 0xffffffffu : 0u;
+    asrc[q] = (size_t)(gi < N ? gi : 0) * Rp + grp * 4;
+  }
+  const int kq = tid % KS, rq = tid / KS;
+  size_t ooff[LOADS], uoff[LOADS];
+  float bmask[LOADS];
+#pragma unroll
+  for (int q = 0; q < LOADS; ++q) {
+    int gt = t0 + rq + 16 * q;
+    bmask[q] = gt < T ? 1.f : 0.f;
+    int t = gt < T ? gt : 0;
+    ooff[q] = (size_t)(t / nu) * R;
+    uoff[q] = (size_t)(t % nu) * R;
+  }
+  uint4 rah[4], ral[4];
+  float2 ro[LOADS], ru[LOADS];
+  float rmask = 1.f;
+  auto gload = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      rah[q] = *reinterpret_cast<const uint4*>(Uh + asrc[q] + r0);
+      ral[q] = *reinterpret_cast<const uint4*>(Ul + asrc[q] + r0);
+    }
+    int r = r0 + kq;
+    rmask = r < R ? 1.f : 0.f;
+    r = r < R ? r : R - 1;
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      ro[q] = po[ooff[q] + r];
+      ru[q] = pu[uoff[q] + r];
+    }
+  };
+  auto store_a = [&](Lds2& L, int q) {
+    uint4 x = rah[q], y = ral[q];
+    x.x &= amask[q]; x.y &= amask[q]; x.z &= amask[q]; x.w &= amask[q];
+    y.x &= amask[q]; y.y &= amask[q]; y.z &= amask[q]; y.w &= amask[q];
+    *reinterpret_cast<uint4*>(&L.ahi[aoff[q]]) = x;
+    *reinterpret_cast<uint4*>(&L.alo[aoff[q]]) = y;
+  };
+  auto store_b = [&](Lds2& L, int q) {
+    const float m = bmask[q] * rmask;
+    const int row = rq + 16 * q;
+    float fr = (ro[q].x * ru[q].x + ro[q].y * ru[q].y) * m;
+    float fi = (ro[q].x * ru[q].y - ro[q].y * ru[q].x) * m;
+    uint32_t hh, ll;
+    split_word<W_BF16>(fr, fi, 1.f, hh, ll);
+    L.bhi[row * SW + kq] = hh;
+    L.blo[row * SW + kq] = ll;
+  };
+  Acc2 acc;
+  acc.zero();
+  const int nst = (R + KS - 1) / KS;
+  gload(0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) store_a(Lb[0], q);
+#pragma unroll
+  for (int q = 0; q < LOADS; ++q) store_b(Lb[0], q);
+  if (nst > 1) gload(KS);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const Lds2& L = Lb[st & 1];
+    Lds2& Ln = Lb[(st + 1) & 1];
+#pragma unroll
+    for (int s = 0; s < KS / 8; ++s) {
+      const int off = s * 8 + h * 4;
+      uint4 brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        int col = wn * 64 + cb * 32 + l32;
+        uint4 bh = *reinterpret_cast<const uint4*>(&L.bhi[col * SW + off]);
+        uint4 bl = *reinterpret_cast<const uint4*>(&L.blo[col * SW + off]);
+        brh[cb] = frag_conj(bh);
+        brl[cb] = frag_conj(bl);
+        bih[cb] = frag_swap(bh);
+        bil[cb] = frag_swap(bl);
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        int row = wm * 128 + rb * 32 + l32;
+        uint4 ah = *reinterpret_cast<const uint4*>(&L.ahi[row * SW + off]);
+        uint4 al = *reinterpret_cast<const uint4*>(&L.alo[row * SW + off]);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          acc.r[rb][cb] = mma16<W_BF16>(ah, brh[cb], acc.r[rb][cb]);
+          acc.i[rb][cb] = mma16<W_BF16>(ah, bih[cb], acc.i[rb][cb]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          acc.r[rb][cb] = mma16<W_BF16>(ah, brl[cb], acc.r[rb][cb]);
+          acc.i[rb][cb] = mma16<W_BF16>(ah, bil[cb], acc.i[rb][cb]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          acc.r[rb][cb] = mma16<W_BF16>(al, brh[cb], acc.r[rb][cb]);
+          acc.i[rb][cb] = mma16<W_BF16>(al, bih[cb], acc.i[rb][cb]);
+        }
+        // staging of the next stage, one slice per MFMA group (after the last
+        // stage this writes the idle buffer, which is never read again)
+        const int g = s * 4 + rb;
+        if (g < 4) store_a(Ln, g);
+        store_b(Ln, g);
+        // 12 MFMAs interleaved with the slice's VALU and LDS work
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        }
+      }
+    }
+    if (st + 2 < nst) gload((st + 2) * KS);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      int gt = t0 + acc_col(wn, cb, lane);
+      if (gt >= T) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int gi = i0 + acc2_row(wm, rb, v, lane);
+        if (gi < N) M[(size_t)gi * ldm + gt] = make_float2(acc.r[rb][cb][v], acc.i[rb][cb][v]);
+      }
+    }
+}
+
 // tile l of the lower part for 256 x 128 tiles: row block bi owns column blocks 0 .. 2 bi + 1
 __device__ inline void lower_tile_2(int l, int& bi, int& bj) {
   int b = (int)((sqrt(4.0 * (double)l + 1.0) - 1.0) * 0.5);
@@ -967,6 +1123,8 @@ int prepare_split(hipStream_t s, int word, int N, int R, int Rp, const float2* U
 
 // Large tiles pay off once the basis spans a few of them.
 constexpr int kLargeTileN = 256;
+int g_proj_variant = 3;   // 1: 128x128 tiles; 2: 256x128; 3: 256x128 software-pipelined
+int g_acc_variant = 1;    // 1: 128x128 tiles; 2: 256x128
 constexpr size_t kLds2Bytes = 2 * sizeof(Lds2);
 
 int enable_large_lds() {
@@ -976,13 +1134,15 @@ int enable_large_lds() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds2Bytes));
   GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&herk_bf16v2_kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds2Bytes));
+  GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&project_bf16v3_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds2Bytes));
   done = 1;
   return GW_OK;
 }
 
 int launch_herk16(hipStream_t s, int word, int N, int T, const float2* M, long ldm, const float* w, int n_omega,
                   double2* P, const Scales* sc) {
-  if (word == W_BF16 && N >= kLargeTileN) {
+  if (word == W_BF16 && g_acc_variant == 2 && N >= kLargeTileN) {
     int st = enable_large_lds();
     if (st != GW_OK) return st;
     int nb = (N + BM2 - 1) / BM2;
@@ -1007,14 +1167,18 @@ int launch_herk16(hipStream_t s, int word, int N, int T, const float2* M, long l
 int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32_t* Uh, const uint32_t* Ul,
                      const float2* po, const float2* pu, int no, int nu, float2* M, long ldm, Scales* sc) {
   int T = no * nu;
-  if (word == W_BF16 && N >= kLargeTileN) {
+  if (word == W_BF16 && g_proj_variant >= 2 && N >= kLargeTileN) {
     int st = enable_large_lds();
     if (st != GW_OK) return st;
     dim3 grid2((T + BN2 - 1) / BN2, (N + BM2 - 1) / BM2);
     ProfScope prof(s, "project_bf16_kernel");
-    hipLaunchKernelGGL(project_bf16v2_kernel, grid2, dim3(NT), kLds2Bytes, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M,
-                       ldm);
-    GW_LAUNCHED("project_bf16v2_kernel");
+    if (g_proj_variant == 3)
+      hipLaunchKernelGGL(project_bf16v3_kernel, grid2, dim3(NT), kLds2Bytes, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M,
+                         ldm);
+    else
+      hipLaunchKernelGGL(project_bf16v2_kernel, grid2, dim3(NT), kLds2Bytes, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M,
+                         ldm);
+    GW_LAUNCHED("project_bf16v2/v3_kernel");
     return GW_OK;
   }
   dim3 grid((T + BN - 1) / BN, (N + BM - 1) / BM);
@@ -1147,3 +1311,19 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
 }
 
 }  // namespace gw
+
+extern "C" int gw_set_tuning(const char* key, int value) {
+  if (!key) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: key is NULL");
+  const std::string k(key);
+  if (k == "projection_variant") {
+    if (value < 1 || value > 3) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: projection_variant is 1, 2 or 3");
+    gw::g_proj_variant = value;
+    return GW_OK;
+  }
+  if (k == "accumulation_variant") {
+    if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: accumulation_variant is 1 or 2");
+    gw::g_acc_variant = value;
+    return GW_OK;
+  }
+  return gw::fail(GW_ERR_INVALID_ARG, std::string("gw_set_tuning: unknown key ") + key);
+}
