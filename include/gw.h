@@ -232,12 +232,12 @@ int gw_surrogate_judge(void* stream, const gw_surr_desc* d_host, const float* Y,
 
 /* --------------------------------------------------------------------- tuning
  * Process-wide kernel-variant switches (all results stay within the same
- * tolerances; the work done is identical).  Keys (split-BF16 path, N >= 256):
- *   "projection_variant"    1: 128 x 128 tiles; 2: 256 x 128 tiles;
- *                           3 (default): 256 x 128 tiles with the staging of
- *                           the next K stage interleaved with the MFMAs.
- *   "accumulation_variant"  1 (default): 128 x 128 tiles; 2: 256 x 128 tiles.
- * Unknown keys give GW_ERR_INVALID_ARG. */
+ * tolerances; the work done is identical).  Keys:
+ *   "projection_variant"  split-BF16 projection for N >= 256:
+ *                         1: 128 x 128 output tiles;
+ *                         2 (default): 256 x 128 output tiles with the staging
+ *                         of the next K stage interleaved with the MFMAs.
+ * Values out of range and unknown keys give GW_ERR_INVALID_ARG. */
 int gw_set_tuning(const char* key_host, int value);
 
 /* ------------------------------------------------------------------ profiling

@@ -27,11 +27,9 @@ namespace {
 bool valid_precision(int p) { return p >= GW_FP64 && p <= GW_SPLIT_FP16; }
 size_t cplx_bytes(int p) { return p == GW_FP64 ? 16 : 8; }
 
-// Chunk sizes for one polarization call.
+// Chunk size for one polarization call.
 struct Plan {
-  int no_c = 0;   // occupied bands per chunk
-  int nu_c = 0;   // unoccupied bands per chunk
-  int tc = 0;     // max pairs per chunk = no_c * nu_c
+  int tc = 0;     // max pairs per chunk
   size_t ws = 0;  // workspace bytes
 };
 
@@ -47,18 +45,8 @@ int default_chunk_pairs(const gw_pol_desc& d) {
 
 Plan make_plan(const gw_pol_desc& d) {
   Plan pl;
-  const int no = d.occ_end - d.occ_begin;
-  const int nu = d.unocc_end - d.unocc_begin;
-  int target = default_chunk_pairs(d);
-  if (nu >= target) {
-    pl.no_c = 1;
-    pl.nu_c = target;
-  } else {
-    pl.nu_c = nu;
-    pl.no_c = std::max(1, std::min(no, target / nu));
-  }
-  if (d.precision != GW_FP64) mfma_adjust_chunk(d.precision, pl.no_c, pl.nu_c, no, nu);
-  pl.tc = pl.no_c * pl.nu_c;
+  const long total = (long)(d.occ_end - d.occ_begin) * (d.unocc_end - d.unocc_begin);
+  pl.tc = (int)std::max(1L, std::min<long>(default_chunk_pairs(d), total));
   if (d.precision == GW_FP64) {
     pl.ws = align_up((size_t)d.N * pl.tc * 16) + align_up((size_t)d.n_omega * pl.tc * sizeof(double));
   } else {
@@ -160,8 +148,8 @@ int gw_project(void* stream, int precision, int N, int R, int n_occ, int n_unocc
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (precision == GW_FP64)
     return launch_project_f64(s, N, R, static_cast<const double2*>(U), static_cast<const double2*>(psi_occ),
-                              static_cast<const double2*>(psi_unocc), n_occ, n_unocc, static_cast<double2*>(M),
-                              (long)n_occ * n_unocc);
+                              static_cast<const double2*>(psi_unocc), n_unocc, 0, n_occ * n_unocc,
+                              static_cast<double2*>(M), (long)n_occ * n_unocc);
   return mfma_project(s, precision, N, R, n_occ, n_unocc, U, psi_occ, psi_unocc, M, ws, ws_bytes);
 }
 
@@ -202,17 +190,19 @@ int gw_polarization(void* stream, const gw_pol_desc* dp, void* ws, size_t ws_byt
   for (int i = 0; i < nk; ++i) {
     int k = d.k_list_host ? d.k_list_host[i] : i;
     int kq = d.kq_host ? d.kq_host[k] : (k + 1) % d.n_k;
-    for (int n0 = d.occ_begin; n0 < d.occ_end; n0 += pl.no_c)
-      for (int u0 = d.unocc_begin; u0 < d.unocc_end; u0 += pl.nu_c) {
-        Chunk c;
-        c.k = k;
-        c.kq = kq;
-        c.n0 = n0;
-        c.no = std::min(pl.no_c, d.occ_end - n0);
-        c.u0 = u0;
-        c.nu = std::min(pl.nu_c, d.unocc_end - u0);
-        chunks.push_back(c);
-      }
+    const int nu = d.unocc_end - d.unocc_begin;
+    const long total = (long)(d.occ_end - d.occ_begin) * nu;
+    for (long tb = 0; tb < total; tb += pl.tc) {
+      Chunk c;
+      c.k = k;
+      c.kq = kq;
+      c.n0 = d.occ_begin;
+      c.u0 = d.unocc_begin;
+      c.nu = nu;
+      c.tb = tb;
+      c.T = (int)std::min<long>(pl.tc, total - tb);
+      chunks.push_back(c);
+    }
   }
   if (d.precision == GW_FP64) {
     Carver cv(ws);
@@ -224,7 +214,7 @@ int gw_polarization(void* stream, const gw_pol_desc* dp, void* ws, size_t ws_byt
       const double2* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
       const double2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
       if ((st = launch_weights_f64(s, d.eps, nb, d.n_occ, c, om, w)) != GW_OK) return st;
-      if ((st = launch_project_f64(s, d.N, d.R, U, po, pu, c.no, c.nu, M, c.pairs())) != GW_OK) return st;
+      if ((st = launch_project_f64(s, d.N, d.R, U, po, pu, c.nu, c.tb, c.T, M, c.T)) != GW_OK) return st;
       if ((st = launch_herk_f64(s, d.N, c.pairs(), M, c.pairs(), w, d.n_omega, P)) != GW_OK) return st;
     }
   } else {

@@ -62,13 +62,17 @@ class ProfScope {
 };
 
 // ---- transition-pair chunk ---------------------------------------------------
-// A chunk is a block of occupied bands [n0, n0+no) of set k times the
-// unoccupied bands [u0, u0+nu) of set kq; pair t = (n-n0)*nu + (n'-u0).
+// A chunk is a run of T consecutive transition pairs of set k (occupied) and
+// set kq (unoccupied).  The pairs of a call form the grid (n, n') with n from
+// n0 and n' from u0 (u0 counts from the first unoccupied band) and nu
+// unoccupied bands per row; chunk pair t is grid index g = tb + t, i.e.
+// n = n0 + g / nu, n' = u0 + g % nu.
 struct Chunk {
   int k, kq;
-  int n0, no;
-  int u0, nu;  // u0 counts from the first unoccupied band
-  int pairs() const { return no * nu; }
+  int n0, u0, nu;
+  long tb;
+  int T;
+  int pairs() const { return T; }
 };
 
 // ---- FP64 path (k_fp64.hip) ----------------------------------------------------
@@ -76,7 +80,7 @@ int launch_fill_zero(hipStream_t s, double* p, size_t n_doubles);
 int launch_weights_f64(hipStream_t s, const double* eps, int n_bands, int n_occ, const Chunk& c,
                        const OmegaList& om, double* w /*[n_omega][pairs]*/);
 int launch_project_f64(hipStream_t s, int N, int R, const double2* U, const double2* psi_occ,
-                       const double2* psi_unocc, int no, int nu, double2* M, long ldm);
+                       const double2* psi_unocc, int nu, long tb, int T, double2* M, long ldm);
 int launch_herk_f64(hipStream_t s, int N, int T, const double2* M, long ldm, const double* w,
                     int n_omega, double2* P);
 int launch_hermitian_mirror(hipStream_t s, int N, int n_omega, double2* P);

@@ -8,7 +8,6 @@
 namespace gw {
 
 int mfma_default_chunk_pairs(int N, int precision);
-void mfma_adjust_chunk(int precision, int& no_c, int& nu_c, int no, int nu);
 size_t mfma_pol_workspace(int precision, int N, int R, int tc, int n_omega);
 size_t mfma_project_workspace(int precision, int N, int R, int n_occ, int n_unocc);
 int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_unocc, const void* U,

@@ -22,10 +22,11 @@ __global__ void fill_zero_kernel(double* __restrict__ p, size_t n) {
 __global__ void weights_f64_kernel(const double* __restrict__ eps, int n_bands, int n_occ, Chunk c,
                                    OmegaList om, double* __restrict__ w) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int T = c.no * c.nu;
+  int T = c.T;
   if (t >= T) return;
-  int n = c.n0 + t / c.nu;
-  int u = c.u0 + t % c.nu;
+  long g = c.tb + t;
+  int n = c.n0 + (int)(g / c.nu);
+  int u = c.u0 + (int)(g % c.nu);
   double d = eps[(size_t)c.k * n_bands + n] - eps[(size_t)c.kq * n_bands + n_occ + u];
   double d2 = d * d;
   for (int j = 0; j < om.n; ++j) w[(size_t)j * T + t] = 4.0 * d / (d2 + om.w[j] * om.w[j]);
@@ -35,11 +36,10 @@ __global__ void weights_f64_kernel(const double* __restrict__ eps, int n_bands, 
 // The product conj(po) * pu is formed while staging the B tile; it is never stored.
 __global__ __launch_bounds__(NT) void project_f64_kernel(int N, int R, const double2* __restrict__ U,
                                                          const double2* __restrict__ po,
-                                                         const double2* __restrict__ pu, int no, int nu,
+                                                         const double2* __restrict__ pu, int nu, long tb, int T,
                                                          double2* __restrict__ M, long ldm) {
   __shared__ double2 As[TK][TM + 1];
   __shared__ double2 Bs[TK][TN + 1];
-  const int T = no * nu;
   const int t0 = blockIdx.x * TN;
   const int i0 = blockIdx.y * TM;
   const int tid = threadIdx.x;
@@ -67,8 +67,9 @@ __global__ __launch_bounds__(NT) void project_f64_kernel(int N, int R, const dou
       int gt = t0 + tt, gr = r0 + kk;
       double2 val = make_double2(0.0, 0.0);
       if (gt < T && gr < R) {
-        double2 a = po[(size_t)(gt / nu) * R + gr];
-        double2 b = pu[(size_t)(gt % nu) * R + gr];
+        long g = tb + gt;
+        double2 a = po[(size_t)(g / nu) * R + gr];
+        double2 b = pu[(size_t)(g % nu) * R + gr];
         // conj(a) * b
         val = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
       }
@@ -228,7 +229,7 @@ int launch_fill_zero(hipStream_t s, double* p, size_t n) {
 
 int launch_weights_f64(hipStream_t s, const double* eps, int n_bands, int n_occ, const Chunk& c,
                        const OmegaList& om, double* w) {
-  int T = c.pairs();
+  int T = c.T;
   hipLaunchKernelGGL(weights_f64_kernel, dim3((T + 255) / 256), dim3(256), 0, s, eps, n_bands, n_occ, c,
                      om, w);
   GW_LAUNCHED("weights_f64_kernel");
@@ -236,11 +237,10 @@ int launch_weights_f64(hipStream_t s, const double* eps, int n_bands, int n_occ,
 }
 
 int launch_project_f64(hipStream_t s, int N, int R, const double2* U, const double2* po,
-                       const double2* pu, int no, int nu, double2* M, long ldm) {
-  int T = no * nu;
+                       const double2* pu, int nu, long tb, int T, double2* M, long ldm) {
   dim3 grid((T + TN - 1) / TN, (N + TM - 1) / TM);
   ProfScope prof(s, "project_f64_kernel");
-  hipLaunchKernelGGL(project_f64_kernel, grid, dim3(NT), 0, s, N, R, U, po, pu, no, nu, M, ldm);
+  hipLaunchKernelGGL(project_f64_kernel, grid, dim3(NT), 0, s, N, R, U, po, pu, nu, tb, T, M, ldm);
   GW_LAUNCHED("project_f64_kernel");
   return GW_OK;
 }

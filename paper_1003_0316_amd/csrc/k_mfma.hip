@@ -89,11 +89,10 @@ __device__ inline int acc_col(int wn, int cb, int lane) { return wn * 64 + cb * 
 // ---------------------------------------------------------------- projection
 __global__ __launch_bounds__(NT, 2) void project_f32_kernel(int N, int R, const float2* __restrict__ U,
                                                             const float2* __restrict__ po,
-                                                            const float2* __restrict__ pu, int no, int nu,
+                                                            const float2* __restrict__ pu, int nu, long tb, int T,
                                                             float2* __restrict__ M, long ldm) {
   __shared__ __attribute__((aligned(16))) float As[BM * AS];
   __shared__ __attribute__((aligned(16))) float Bs[BN * BS];
-  const int T = no * nu;
   const int t0 = blockIdx.x * BN;
   const int i0 = blockIdx.y * BM;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -114,8 +113,9 @@ __global__ __launch_bounds__(NT, 2) void project_f32_kernel(int N, int R, const 
     int gt = t0 + rq + 16 * q;
     bok[q] = gt < T;
     int t = bok[q] ? gt : 0;
-    orow[q] = po + (size_t)(t / nu) * R;
-    urow[q] = pu + (size_t)(t % nu) * R;
+    const long g = tb + t;
+    orow[q] = po + (size_t)(g / nu) * R;
+    urow[q] = pu + (size_t)(g % nu) * R;
   }
   float2 ra[LOADS], ro[LOADS], ru[LOADS];
   auto gload = [&](int r0) {
@@ -238,21 +238,21 @@ __global__ __launch_bounds__(NT, 2) void herk_f32_kernel(int N, int T, const flo
 __global__ void weights_f32_kernel(const double* __restrict__ eps, int n_bands, int n_occ, Chunk c, OmegaList om,
                                    float* __restrict__ w) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int T = c.no * c.nu;
+  int T = c.T;
   if (t >= T) return;
-  int n = c.n0 + t / c.nu;
-  int u = c.u0 + t % c.nu;
+  long g = c.tb + t;
+  int n = c.n0 + (int)(g / c.nu);
+  int u = c.u0 + (int)(g % c.nu);
   double d = eps[(size_t)c.k * n_bands + n] - eps[(size_t)c.kq * n_bands + n_occ + u];
   double d2 = d * d;
   for (int j = 0; j < om.n; ++j) w[(size_t)j * T + t] = (float)(4.0 * d / (d2 + om.w[j] * om.w[j]));
 }
 
-int launch_project_f32(hipStream_t s, int N, int R, const float2* U, const float2* po, const float2* pu, int no,
-                       int nu, float2* M, long ldm) {
-  int T = no * nu;
+int launch_project_f32(hipStream_t s, int N, int R, const float2* U, const float2* po, const float2* pu, int nu,
+                       long tb, int T, float2* M, long ldm) {
   dim3 grid((T + BN - 1) / BN, (N + BM - 1) / BM);
   ProfScope prof(s, "project_f32_kernel");
-  hipLaunchKernelGGL(project_f32_kernel, grid, dim3(NT), 0, s, N, R, U, po, pu, no, nu, M, ldm);
+  hipLaunchKernelGGL(project_f32_kernel, grid, dim3(NT), 0, s, N, R, U, po, pu, nu, tb, T, M, ldm);
   GW_LAUNCHED("project_f32_kernel");
   return GW_OK;
 }
@@ -424,13 +424,12 @@ __global__ void split_u_kernel(int N, int R, int Rp, const float2* __restrict__ 
 
 // Projection with pre-split U and products split while staging.
 template <int WORD>
-__global__ __launch_bounds__(NT, 1) void project16_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
+__global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void project16_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
                                                           const uint32_t* __restrict__ Ul,
                                                           const float2* __restrict__ po,
-                                                          const float2* __restrict__ pu, int no, int nu,
+                                                          const float2* __restrict__ pu, int nu, long tb, int T,
                                                           float2* __restrict__ M, long ldm, Scales* __restrict__ sc) {
   __shared__ __attribute__((aligned(16))) Lds16 L;
-  const int T = no * nu;
   const int t0 = blockIdx.x * BN;
   const int i0 = blockIdx.y * BM;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -441,50 +440,58 @@ __global__ __launch_bounds__(NT, 1) void project16_kernel(int N, int R, int Rp, 
     sF = pow2_scale(2.f * mp * mp);
     unscale = 1.f / (pow2_scale(__uint_as_float(sc->u)) * sF);
   }
-  // A staging: 128 rows x 4 groups of 4 complex; two (row, group) slots per thread
+  // A staging: 128 rows x 4 groups of 4 complex; two (row, group) slots per
+  // thread.  Offsets are 32-bit and relative to the tile's first row (rows past
+  // N read the tile's first row and are zeroed), so the kernel fits two waves
+  // per SIMD.
+  const uint32_t* UhT = Uh + (size_t)i0 * Rp;
+  const uint32_t* UlT = Ul + (size_t)i0 * Rp;
   int arow_l[2], agrp[2];
-  const uint32_t* ah_src[2];
-  const uint32_t* al_src[2];
-  bool aok[2];
+  uint32_t asrc[2], amask[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     int e = tid + q * NT;
     arow_l[q] = e >> 2;
     agrp[q] = e & 3;
     int gi = i0 + arow_l[q];
-    aok[q] = gi < N;
-    size_t base = (size_t)(aok[q] ? gi : 0) * Rp + agrp[q] * 4;
-    ah_src[q] = Uh + base;
-    al_src[q] = Ul + base;
+    amask[q] = gi < N ? 0xffffffffu : 0u;
+    asrc[q] = (uint32_t)((size_t)((gi < N ? gi : i0) - i0) * Rp + agrp[q] * 4);
   }
   // B staging as in the FP32 kernel: pair rq + 16 q, complex k kq
   const int kq = tid % KS, rq = tid / KS;
-  const float2* orow[LOADS];
-  const float2* urow[LOADS];
-  bool bok[LOADS];
+  uint32_t ooff[LOADS], uoff[LOADS];
+  float bmask[LOADS];
 #pragma unroll
   for (int q = 0; q < LOADS; ++q) {
     int gt = t0 + rq + 16 * q;
-    bok[q] = gt < T;
-    int t = bok[q] ? gt : 0;
-    orow[q] = po + (size_t)(t / nu) * R;
-    urow[q] = pu + (size_t)(t % nu) * R;
+    bmask[q] = gt < T ? 1.f : 0.f;
+    int t = gt < T ? gt : 0;
+    const long g = tb + t;
+    ooff[q] = (uint32_t)((size_t)(g / nu) * R);
+    uoff[q] = (uint32_t)((size_t)(g % nu) * R);
   }
   uint4 rah[2], ral[2];
   float2 ro[LOADS], ru[LOADS];
+  float rmask = 1.f;
   auto gload = [&](int r0) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      rah[q] = aok[q] ? *reinterpret_cast<const uint4*>(ah_src[q] + r0) : make_uint4(0, 0, 0, 0);
-      ral[q] = aok[q] ? *reinterpret_cast<const uint4*>(al_src[q] + r0) : make_uint4(0, 0, 0, 0);
+      uint4 x = *reinterpret_cast<const uint4*>(UhT + asrc[q] + r0);
+      uint4 y = *reinterpret_cast<const uint4*>(UlT + asrc[q] + r0);
+      x.x &= amask[q]; x.y &= amask[q]; x.z &= amask[q]; x.w &= amask[q];
+      y.x &= amask[q]; y.y &= amask[q]; y.z &= amask[q]; y.w &= amask[q];
+      rah[q] = x;
+      ral[q] = y;
     }
     int r = r0 + kq;
-    bool rok = r < R;
+    rmask = r < R ? 1.f : 0.f;
+    r = r < R ? r : R - 1;
 #pragma unroll
     for (int q = 0; q < LOADS; ++q) {
-      bool ok = bok[q] && rok;
-      ro[q] = ok ? orow[q][r] : make_float2(0.f, 0.f);
-      ru[q] = ok ? urow[q][r] : make_float2(0.f, 0.f);
+      float m = bmask[q] * rmask;
+      float2 o = po[ooff[q] + r], u = pu[uoff[q] + r];
+      ro[q] = make_float2(o.x * m, o.y * m);
+      ru[q] = u;
     }
   };
   AccF32 acc, acc2;
@@ -642,11 +649,12 @@ __global__ void weights_f32_max_kernel(const double* __restrict__ eps, int n_ban
                                        float* __restrict__ w, Scales* __restrict__ sc) {
   __shared__ float red[256];
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int T = c.no * c.nu;
+  int T = c.T;
   double d = 0.0;
   if (t < T) {
-    int n = c.n0 + t / c.nu;
-    int u = c.u0 + t % c.nu;
+    long g = c.tb + t;
+    int n = c.n0 + (int)(g / c.nu);
+    int u = c.u0 + (int)(g % c.nu);
     d = eps[(size_t)c.k * n_bands + n] - eps[(size_t)c.kq * n_bands + n_occ + u];
   }
   for (int j = 0; j < om.n; ++j) {
@@ -733,119 +741,18 @@ __device__ inline int acc2_row(int wm, int rb, int v, int lane) {
   return wm * 128 + rb * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
 }
 
-// Projection, BF16 words, 256 x 128 tiles.
-__global__ __launch_bounds__(NT, 1) void project_bf16v2_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
-                                                               const uint32_t* __restrict__ Ul,
-                                                               const float2* __restrict__ po,
-                                                               const float2* __restrict__ pu, int no, int nu,
-                                                               float2* __restrict__ M, long ldm) {
-  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
-  Lds2* Lb = reinterpret_cast<Lds2*>(lds_raw);
-  const int T = no * nu;
-  const int t0 = blockIdx.x * BN2;
-  const int i0 = blockIdx.y * BM2;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  // A staging: 256 rows x 4 groups of 4 complex -> 4 (row, group) slots per thread
-  int aoff[4];
-  bool aok[4];
-  size_t asrc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + q * NT;
-    int row = e >> 2, grp = e & 3;
-    aoff[q] = row * SW + grp * 4;
-    int gi = i0 + row;
-    aok[q] = gi < N;
-    asrc[q] = (size_t)(aok[q] ? gi : 0) * Rp + grp * 4;
-  }
-  // B staging: pair rq + 16 q (q < 8), complex k kq
-  const int kq = tid % KS, rq = tid / KS;
-  size_t ooff[LOADS], uoff[LOADS];
-  bool bok[LOADS];
-#pragma unroll
-  for (int q = 0; q < LOADS; ++q) {
-    int gt = t0 + rq + 16 * q;
-    bok[q] = gt < T;
-    int t = bok[q] ? gt : 0;
-    ooff[q] = (size_t)(t / nu) * R;
-    uoff[q] = (size_t)(t % nu) * R;
-  }
-  uint4 rah[4], ral[4];
-  float2 ro[LOADS], ru[LOADS];
-  auto gload = [&](int r0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      rah[q] = aok[q] ? *reinterpret_cast<const uint4*>(Uh + asrc[q] + r0) : make_uint4(0, 0, 0, 0);
-      ral[q] = aok[q] ? *reinterpret_cast<const uint4*>(Ul + asrc[q] + r0) : make_uint4(0, 0, 0, 0);
-    }
-    int r = r0 + kq;
-    bool rok = r < R;
-#pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      bool ok = bok[q] && rok;
-      ro[q] = ok ? po[ooff[q] + r] : make_float2(0.f, 0.f);
-      ru[q] = ok ? pu[uoff[q] + r] : make_float2(0.f, 0.f);
-    }
-  };
-  auto lstore = [&](Lds2& L) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<uint4*>(&L.ahi[aoff[q]]) = rah[q];
-      *reinterpret_cast<uint4*>(&L.alo[aoff[q]]) = ral[q];
-    }
-#pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      int row = rq + 16 * q;
-      float fr = ro[q].x * ru[q].x + ro[q].y * ru[q].y;
-      float fi = ro[q].x * ru[q].y - ro[q].y * ru[q].x;
-      uint32_t hh, ll;
-      split_word<W_BF16>(fr, fi, 1.f, hh, ll);
-      L.bhi[row * SW + kq] = hh;
-      L.blo[row * SW + kq] = ll;
-    }
-  };
-  Acc2 acc;
-  acc.zero();
-  gload(0);
-  lstore(Lb[0]);
-  __syncthreads();
-  int buf = 0;
-  for (int r0 = 0; r0 < R; r0 += KS) {
-    const bool more = r0 + KS < R;
-    if (more) gload(r0 + KS);
-    mma_stage_v2(Lb[buf], acc, wm, wn, lane);
-    if (more) lstore(Lb[buf ^ 1]);
-    __syncthreads();
-    buf ^= 1;
-  }
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      int gt = t0 + acc_col(wn, cb, lane);
-      if (gt >= T) continue;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        int gi = i0 + acc2_row(wm, rb, v, lane);
-        if (gi < N) M[(size_t)gi * ldm + gt] = make_float2(acc.r[rb][cb][v], acc.i[rb][cb][v]);
-      }
-    }
-}
-
 // Projection, BF16 words, 256 x 128 tiles, software-pipelined: the staging of
 // stage s+1 (product, hi/lo split, LDS stores) is spread between the MFMA
 // groups of stage s so that it issues in the shadow of the matrix cores, and
 // global loads run one full stage ahead.  Loads are branch-free (addresses
 // clamped inside the arrays, values zeroed by selects).
-__global__ __launch_bounds__(NT, 1) void project_bf16v3_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
+__global__ __launch_bounds__(NT, 1) void project_bf16_large_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
                                                                const uint32_t* __restrict__ Ul,
                                                                const float2* __restrict__ po,
-                                                               const float2* __restrict__ pu, int no, int nu,
+                                                               const float2* __restrict__ pu, int nu, long tb, int T,
                                                                float2* __restrict__ M, long ldm) {
   extern __shared__ __attribute__((aligned(16))) char lds_raw[];
   Lds2* Lb = reinterpret_cast<Lds2*>(lds_raw);
-  const int T = no * nu;
   const int t0 = blockIdx.x * BN2;
   const int i0 = blockIdx.y * BM2;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -871,8 +778,9 @@ __global__ __launch_bounds__(NT, 1) void project_bf16v3_kernel(int N, int R, int
     int gt = t0 + rq + 16 * q;
     bmask[q] = gt < T ? 1.f : 0.f;
     int t = gt < T ? gt : 0;
-    ooff[q] = (size_t)(t / nu) * R;
-    uoff[q] = (size_t)(t % nu) * R;
+    const long g = tb + t;
+    ooff[q] = (size_t)(g / nu) * R;
+    uoff[q] = (size_t)(g % nu) * R;
   }
   uint4 rah[4], ral[4];
   float2 ro[LOADS], ru[LOADS];
@@ -988,105 +896,6 @@ __global__ __launch_bounds__(NT, 1) void project_bf16v3_kernel(int N, int R, int
     }
 }
 
-// tile l of the lower part for 256 x 128 tiles: row block bi owns column blocks 0 .. 2 bi + 1
-__device__ inline void lower_tile_2(int l, int& bi, int& bj) {
-  int b = (int)((sqrt(4.0 * (double)l + 1.0) - 1.0) * 0.5);
-  while ((b + 1) * (b + 2) <= l) ++b;
-  while (b * (b + 1) > l) --b;
-  bi = b;
-  bj = l - b * (b + 1);
-}
-
-// Accumulation, BF16 words, 256 x 128 tiles (rows I, columns J).
-__global__ __launch_bounds__(NT, 1) void herk_bf16v2_kernel(int N, int T, const float2* __restrict__ M, long ldm,
-                                                            const float* __restrict__ w, double2* __restrict__ P) {
-  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
-  Lds2* Lb = reinterpret_cast<Lds2*>(lds_raw);
-  int bi, bj;
-  lower_tile_2(blockIdx.x, bi, bj);
-  const int i0 = bi * BM2, j0 = bj * BN2;
-  if (j0 >= N) return;
-  const int om = blockIdx.y;
-  const float* wj = w + (size_t)om * T;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  const int kq = tid % KS, rq = tid / KS;
-  // A rows rq + 16 q (q < 16), B rows rq + 16 q (q < 8)
-  size_t aoff[16], boff[LOADS];
-  bool aok[16], bok[LOADS];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    int gi = i0 + rq + 16 * q;
-    aok[q] = gi < N;
-    aoff[q] = (size_t)(aok[q] ? gi : 0) * ldm;
-  }
-#pragma unroll
-  for (int q = 0; q < LOADS; ++q) {
-    int gj = j0 + rq + 16 * q;
-    bok[q] = gj < N;
-    boff[q] = (size_t)(bok[q] ? gj : 0) * ldm;
-  }
-  float2 ra[16], rb_[LOADS];
-  float rw;
-  auto gload = [&](int t0) {
-    int t = t0 + kq;
-    bool tok = t < T;
-    rw = tok ? wj[t] : 0.f;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) ra[q] = (aok[q] && tok) ? M[aoff[q] + t] : make_float2(0.f, 0.f);
-#pragma unroll
-    for (int q = 0; q < LOADS; ++q) rb_[q] = (bok[q] && tok) ? M[boff[q] + t] : make_float2(0.f, 0.f);
-  };
-  auto lstore = [&](Lds2& L) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      uint32_t hh, ll;
-      split_word<W_BF16>(ra[q].x * rw, ra[q].y * rw, 1.f, hh, ll);
-      L.ahi[(rq + 16 * q) * SW + kq] = hh;
-      L.alo[(rq + 16 * q) * SW + kq] = ll;
-    }
-#pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      uint32_t hh, ll;
-      split_word<W_BF16>(rb_[q].x, -rb_[q].y, 1.f, hh, ll);
-      L.bhi[(rq + 16 * q) * SW + kq] = hh;
-      L.blo[(rq + 16 * q) * SW + kq] = ll;
-    }
-  };
-  Acc2 acc;
-  acc.zero();
-  gload(0);
-  lstore(Lb[0]);
-  __syncthreads();
-  int buf = 0;
-  for (int t0 = 0; t0 < T; t0 += KS) {
-    const bool more = t0 + KS < T;
-    if (more) gload(t0 + KS);
-    mma_stage_v2(Lb[buf], acc, wm, wn, lane);
-    if (more) lstore(Lb[buf ^ 1]);
-    __syncthreads();
-    buf ^= 1;
-  }
-  double2* Pj = P + (size_t)om * N * N;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      int gj = j0 + acc_col(wn, cb, lane);
-      if (gj >= N) continue;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        int gi = i0 + acc2_row(wm, rb, v, lane);
-        if (gi < N) {
-          double2 p = Pj[(size_t)gi * N + gj];
-          p.x += (double)acc.r[rb][cb][v];
-          p.y += (double)acc.i[rb][cb][v];
-          Pj[(size_t)gi * N + gj] = p;
-        }
-      }
-    }
-}
-
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 int launch_zero_u32(hipStream_t s, unsigned* p, int n) {
@@ -1123,18 +932,13 @@ int prepare_split(hipStream_t s, int word, int N, int R, int Rp, const float2* U
 
 // Large tiles pay off once the basis spans a few of them.
 constexpr int kLargeTileN = 256;
-int g_proj_variant = 3;   // 1: 128x128 tiles; 2: 256x128; 3: 256x128 software-pipelined
-int g_acc_variant = 1;    // 1: 128x128 tiles; 2: 256x128
+int g_proj_variant = 2;   // 1: 128x128 tiles; 2: 256x128 software-pipelined (BF16 words only)
 constexpr size_t kLds2Bytes = 2 * sizeof(Lds2);
 
 int enable_large_lds() {
   static int done = 0;
   if (done) return GW_OK;
-  GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&project_bf16v2_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds2Bytes));
-  GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&herk_bf16v2_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds2Bytes));
-  GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&project_bf16v3_kernel),
+  GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&project_bf16_large_kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds2Bytes));
   done = 1;
   return GW_OK;
@@ -1142,15 +946,6 @@ int enable_large_lds() {
 
 int launch_herk16(hipStream_t s, int word, int N, int T, const float2* M, long ldm, const float* w, int n_omega,
                   double2* P, const Scales* sc) {
-  if (word == W_BF16 && g_acc_variant == 2 && N >= kLargeTileN) {
-    int st = enable_large_lds();
-    if (st != GW_OK) return st;
-    int nb = (N + BM2 - 1) / BM2;
-    ProfScope prof(s, "herk_bf16_kernel");
-    hipLaunchKernelGGL(herk_bf16v2_kernel, dim3(nb * (nb + 1), n_omega), dim3(NT), kLds2Bytes, s, N, T, M, ldm, w, P);
-    GW_LAUNCHED("herk_bf16v2_kernel");
-    return GW_OK;
-  }
   const int ntile = (N + BM - 1) / BM;
   dim3 hgrid(ntile * (ntile + 1) / 2, n_omega);
   if (word == W_BF16) {
@@ -1165,29 +960,24 @@ int launch_herk16(hipStream_t s, int word, int N, int T, const float2* M, long l
 }
 
 int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32_t* Uh, const uint32_t* Ul,
-                     const float2* po, const float2* pu, int no, int nu, float2* M, long ldm, Scales* sc) {
-  int T = no * nu;
-  if (word == W_BF16 && g_proj_variant >= 2 && N >= kLargeTileN) {
+                     const float2* po, const float2* pu, int nu, long tb, int T, float2* M, long ldm, Scales* sc) {
+  if (word == W_BF16 && g_proj_variant == 2 && N >= kLargeTileN) {
     int st = enable_large_lds();
     if (st != GW_OK) return st;
     dim3 grid2((T + BN2 - 1) / BN2, (N + BM2 - 1) / BM2);
     ProfScope prof(s, "project_bf16_kernel");
-    if (g_proj_variant == 3)
-      hipLaunchKernelGGL(project_bf16v3_kernel, grid2, dim3(NT), kLds2Bytes, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M,
-                         ldm);
-    else
-      hipLaunchKernelGGL(project_bf16v2_kernel, grid2, dim3(NT), kLds2Bytes, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M,
-                         ldm);
-    GW_LAUNCHED("project_bf16v2/v3_kernel");
+    hipLaunchKernelGGL(project_bf16_large_kernel, grid2, dim3(NT), kLds2Bytes, s, N, R, Rp, Uh, Ul, po, pu, nu, tb, T,
+                       M, ldm);
+    GW_LAUNCHED("project_bf16_large_kernel");
     return GW_OK;
   }
   dim3 grid((T + BN - 1) / BN, (N + BM - 1) / BM);
   if (word == W_BF16) {
     ProfScope prof(s, "project_bf16_kernel");
-    hipLaunchKernelGGL(project16_kernel<W_BF16>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M, ldm, sc);
+    hipLaunchKernelGGL(project16_kernel<W_BF16>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, nu, tb, T, M, ldm, sc);
   } else {
     ProfScope prof(s, "project_f16_kernel");
-    hipLaunchKernelGGL(project16_kernel<W_F16>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, no, nu, M, ldm, sc);
+    hipLaunchKernelGGL(project16_kernel<W_F16>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, nu, tb, T, M, ldm, sc);
   }
   GW_LAUNCHED("project16_kernel");
   return GW_OK;
@@ -1195,15 +985,26 @@ int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32
 
 }  // namespace
 
+// Pairs per chunk: a multiple of the 128-pair tile width, at most 8192 and
+// with the c64 M chunk under 256 MB (it is re-read by the accumulation), chosen
+// so that the projection's workgroups fill whole rounds of the 256 CUs.
 int mfma_default_chunk_pairs(int N, int precision) {
-  (void)precision;
-  size_t target = (size_t)192 << 20;  // M chunk bytes (c64)
-  size_t p = target / ((size_t)N * 8);
-  p = std::max<size_t>(BN, std::min<size_t>(p, 4096));
-  return (int)p;
+  const int tile_rows = (precision == GW_SPLIT_BF16 && g_proj_variant == 2 && N >= kLargeTileN) ? BM2 : BM;
+  const long rows = (N + tile_rows - 1) / tile_rows;
+  const long cap = std::max<long>(1, std::min<long>(64, (256L << 20) / ((long)N * 8 * BN)));
+  long best_x = cap;
+  double best_eff = -1.0;
+  for (long x = cap; x >= std::min<long>(cap, 8); --x) {
+    long w = rows * x;
+    double eff = (double)w / (double)(((w + 255) / 256) * 256);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best_x = x;
+    }
+  }
+  return (int)(best_x * BN);
 }
 
-void mfma_adjust_chunk(int, int&, int&, int, int) {}
 
 static size_t split_u_bytes(int precision, int N, int R) {
   if (precision == GW_FP32) return 0;
@@ -1229,8 +1030,8 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
   (void)ws_bytes;
   if (precision == GW_FP32)
     return launch_project_f32(s, N, R, static_cast<const float2*>(U), static_cast<const float2*>(psi_occ),
-                              static_cast<const float2*>(psi_unocc), n_occ, n_unocc, static_cast<float2*>(M),
-                              (long)n_occ * n_unocc);
+                              static_cast<const float2*>(psi_unocc), n_unocc, 0, n_occ * n_unocc,
+                              static_cast<float2*>(M), (long)n_occ * n_unocc);
   const int word = word_of(precision);
   const int Rp = round_up(R, KS);
   Carver cv(ws);
@@ -1254,8 +1055,8 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
     return st;
   }
   return launch_project16(s, word, N, R, Rp, Uh, Ul, static_cast<const float2*>(psi_occ),
-                          static_cast<const float2*>(psi_unocc), n_occ, n_unocc, static_cast<float2*>(M),
-                          (long)n_occ * n_unocc, sc);
+                          static_cast<const float2*>(psi_unocc), n_unocc, 0, n_occ * n_unocc,
+                          static_cast<float2*>(M), (long)n_occ * n_unocc, sc);
 }
 
 int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
@@ -1298,12 +1099,13 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
     const float2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
     dim3 hgrid(ntile * (ntile + 1) / 2, d.n_omega);
     if (!split) {
-      if ((st = launch_project_f32(s, d.N, d.R, U, po, pu, c.no, c.nu, M, T)) != GW_OK) return st;
+      if ((st = launch_project_f32(s, d.N, d.R, U, po, pu, c.nu, c.tb, T, M, T)) != GW_OK) return st;
       ProfScope prof(s, "herk_f32_kernel");
       hipLaunchKernelGGL(herk_f32_kernel, hgrid, dim3(NT), 0, s, d.N, T, M, (long)T, w, P);
       GW_LAUNCHED("herk_f32_kernel");
     } else {
-      if ((st = launch_project16(s, word, d.N, d.R, Rp, Uh, Ul, po, pu, c.no, c.nu, M, T, sc)) != GW_OK) return st;
+      if ((st = launch_project16(s, word, d.N, d.R, Rp, Uh, Ul, po, pu, c.nu, c.tb, T, M, T, sc)) != GW_OK)
+        return st;
       if ((st = launch_herk16(s, word, d.N, T, M, (long)T, w, d.n_omega, P, sc)) != GW_OK) return st;
     }
   }
@@ -1316,13 +1118,8 @@ extern "C" int gw_set_tuning(const char* key, int value) {
   if (!key) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: key is NULL");
   const std::string k(key);
   if (k == "projection_variant") {
-    if (value < 1 || value > 3) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: projection_variant is 1, 2 or 3");
+    if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: projection_variant is 1 or 2");
     gw::g_proj_variant = value;
-    return GW_OK;
-  }
-  if (k == "accumulation_variant") {
-    if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: accumulation_variant is 1 or 2");
-    gw::g_acc_variant = value;
     return GW_OK;
   }
   return gw::fail(GW_ERR_INVALID_ARG, std::string("gw_set_tuning: unknown key ") + key);

@@ -132,24 +132,23 @@ def test_poisoned_workspace(lib, prec):
     assert torch.equal(P1, P2)
 
 
-@pytest.mark.parametrize("pv,av", [(1, 1), (2, 1), (3, 1), (3, 2), (2, 2)])
-def test_split_bf16_kernel_variants(lib, pv, av):
-    """Every tile variant of the split-BF16 path meets the same bar (N spans
-    two 256-row tiles with a ragged tail; R and the pair count are ragged)."""
+@pytest.mark.parametrize("pv", [1, 2])
+def test_split_bf16_kernel_variants(lib, pv):
+    """Every tile variant of the split-BF16 projection meets the same bar (N
+    spans two 256-row tiles with a ragged tail; R and the pair count are
+    ragged)."""
     import torch
     shape = dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150)
     inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=9, omega=gwsynth.omega_mesh("m16"))
     U, psi = _dev(inp)
     try:
         lib.gw_set_tuning("projection_variant", pv)
-        lib.gw_set_tuning("accumulation_variant", av)
         P = lib.gw_polarization(U, psi, inp.eps, inp.omega, 3, precision="split_bf16", kq=inp.kq)
         torch.cuda.synchronize()
     finally:
-        lib.gw_set_tuning("projection_variant", 3)
-        lib.gw_set_tuning("accumulation_variant", 1)
+        lib.gw_set_tuning("projection_variant", 2)
     Ur, pr = _rounded(inp)
     ref = orc.polarization(Ur, pr, inp.eps, inp.omega, 3, kq=inp.kq)
     err = orc.rel_fro(P.cpu().numpy(), ref)
-    print(f"variant projection {pv} accumulation {av}: max rel err {err.max():.2e}")
+    print(f"projection variant {pv}: max rel err {err.max():.2e}")
     assert err.max() < TOL
