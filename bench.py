@@ -49,12 +49,15 @@ def parse():
     ap.add_argument("--cutoff", type=int, default=None, help="explicit unoccupied bands (default: workload's)")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for cpu_baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time for cpu_baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM traffic counters)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv outputs (bench run, then the copy "
                          "calibration) into the traffic file")
+    ap.add_argument("--traffic-driver", action="store_true",
+                    help="only run the main explicit-band polarization of one k-point on Gaussian inputs of the "
+                         "workload's shape (no device QR; the launch sequence for HBM traffic counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c5.json"),
                     help="measured per-launch HBM traffic of the dominant kernel (from rocprofv3 --pmc)")
     return ap.parse_args()
@@ -76,6 +79,37 @@ def copy_calibration() -> int:
     return 0
 
 
+def traffic_driver(a) -> int:
+    """One k-point of the bench's explicit-band polarization (same N, R,
+    occupied bands, cutoff, frequencies and chunking) on unorthogonalised
+    Gaussian inputs: the projection / accumulation launches and their memory
+    traffic depend on the shapes only."""
+    import numpy as np
+    import torch
+
+    import gwsynth
+    from paper_1003_0316_amd import binding as gw
+    dev = torch.device("cuda:0")
+    shp = gwsynth.SHAPES[a.workload]
+    cutoff = a.cutoff or shp.n_unocc_cut or shp.n_unocc
+    g = torch.Generator(device=dev)
+    g.manual_seed(20100316)
+
+    def cgauss(*shape):
+        return torch.complex(torch.randn(*shape, device=dev, generator=g),
+                             torch.randn(*shape, device=dev, generator=g)) / np.sqrt(2.0 * shape[-1])
+    U = cgauss(shp.N, shp.R)
+    psi = cgauss(1, shp.n_occ + cutoff, shp.R)
+    rng = np.random.default_rng(20100316)
+    eps = np.concatenate([np.sort(rng.uniform(-0.5, 0.0, shp.n_occ)), np.sort(rng.uniform(0.02, 2.0, cutoff))])[None]
+    omega = gwsynth.omega_mesh("m16")
+    call = gw.PolarizationCall(U, psi, eps, omega, shp.n_occ, precision=a.precision, kq=[0])
+    call.run()
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_driver": a.workload, "pairs": shp.n_occ * cutoff, "precision": a.precision}))
+    return 0
+
+
 def _pmc_means(d: str, counter: str) -> dict:
     """mean counter value per dispatch, by kernel name, from rocprofv3 csv output"""
     import csv
@@ -86,11 +120,10 @@ def _pmc_means(d: str, counter: str) -> dict:
             for row in csv.DictReader(fh):
                 if row.get("Counter_Name") != counter:
                     continue
-                name = row.get("Kernel_Name", "")
-                key = name.split("(")[0].replace("gw::(anonymous namespace)::", "")
-                for pre in ("gw::(anonymous namespace)::", "void "):
-                    if key.startswith(pre):
-                        key = key[len(pre):]
+                name = row.get("Kernel_Name", "").replace("gw::(anonymous namespace)::", "")
+                if name.startswith("void "):
+                    name = name[len("void "):]
+                key = name.split("(")[0]
                 acc.setdefault(key, []).append(float(row["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
@@ -110,9 +143,11 @@ def summarize_pmc(a) -> int:
         fb = fetch.get(k, 0.0) * 1024.0 * (kf or 1.0)
         wb = write.get(k, 0.0) * 1024.0 * (kw or 1.0)
         out["kernels"][k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
-    dom = "project_bf16v2_kernel" if "project_bf16v2_kernel" in out["kernels"] else None
+    # the projection runs as the OUT_TILED instance of the split-BF16 GEMM core
+    dom = next((k for k in out["kernels"] if k.startswith("gemm_bf16x3_kernel<0,")), None)
     if dom:
         out["kernel"] = "project_bf16_kernel"
+        out["symbol"] = dom
         out["bytes_per_launch"] = out["kernels"][dom]["fetch_bytes_per_launch"] + \
             out["kernels"][dom]["write_bytes_per_launch"]
     with open(a.traffic, "w") as fh:
@@ -124,7 +159,7 @@ def summarize_pmc(a) -> int:
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_mfma.hip",):
+    for f in ("k_mfma.hip", "k_tiled.hip"):
         with open(os.path.join(ROOT, "paper_1003_0316_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -136,6 +171,8 @@ def main() -> int:
         return copy_calibration()
     if a.summarize_pmc:
         return summarize_pmc(a)
+    if a.traffic_driver:
+        return traffic_driver(a)
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build runs on one GPU only "
               f"(the k-point / occupied-band shards and the reduce-scatter of P over frequencies are "
@@ -209,7 +246,8 @@ def main() -> int:
 
     pre = "bf16" if a.precision == "split_bf16" else ("f16" if a.precision == "split_fp16" else "f32")
     kernels = {}
-    for name in (f"project_{pre}_kernel", f"herk_{pre}_kernel", "update_kernel", "apply_kernel"):
+    for name in (f"project_{pre}_kernel", f"herk_{pre}_kernel", "pair_product_kernel", "scale_split_kernel",
+                 "update_kernel", "apply_kernel"):
         n, tot = gw.gw_profile_query(name)
         kernels[name] = {"launches": n, "total_ms": tot}
     T_pairs = shp.n_k * shp.n_occ * cutoff
@@ -224,7 +262,7 @@ def main() -> int:
     flops_acc = 4.0 * N * (N + 1) * T_run * n_om
     flops_screen = 0.5 * N ** 3 * 8.0 * n_om
     per_step = {f"project_{pre}_kernel": flops_proj, f"herk_{pre}_kernel": flops_acc, "update_kernel": flops_screen,
-                "apply_kernel": 0.0}
+                "pair_product_kernel": 0.0, "scale_split_kernel": 0.0, "apply_kernel": 0.0}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dk = kernels[dom]
     avg_ms = dk["total_ms"] / max(1, dk["launches"])
@@ -312,16 +350,18 @@ def main() -> int:
             return time.time() - tc
         ta, tb = oracle_time(4), oracle_time(16)
         per_pair = max((tb - ta) / 12.0, 1e-4)
-        m2 = int(min(cutoff, max(16, (a.cpu_seconds - ta) / per_pair)))
+        want = max(16, int((a.cpu_seconds - ta) / per_pair))
+        o2 = int(min(occ_p, max(1, -(-want // cutoff))))     # occupied bands in the sample
+        m2 = int(min(cutoff, max(16, -(-want // o2))))       # unoccupied bands per occupied band
         tc = time.time()
-        orc.polarization(U_h, psi_h, inp.eps, inp.omega, shp.n_occ, kq=inp.kq, k_list=[0], occ_range=(0, 1),
+        orc.polarization(U_h, psi_h, inp.eps, inp.omega, shp.n_occ, kq=inp.kq, k_list=[0], occ_range=(0, o2),
                          unocc_range=(0, m2))
         dt2 = time.time() - tc
-        scale = T_pairs / m2
+        scale = T_pairs / (o2 * m2)
         cpu = {"value": round(dt2 * scale, 1), "unit": "s/q-point", "cores": cores, "kind": "oracle",
-               "sample": f"k=0, occupied band 0 x unoccupied 0..{m2 - 1} ({m2} pairs, full basis, all {n_om} "
-                         f"frequencies) in {dt2:.1f} s, scaled x{scale:.0f} to the {T_pairs} pairs of a q-point"}
-        log(f"cpu oracle: {dt2:.1f} s for {m2} pairs -> {dt2 * scale:.0f} s/q-point extrapolated")
+               "sample": f"k=0, occupied 0..{o2 - 1} x unoccupied 0..{m2 - 1} ({o2 * m2} pairs, full basis, all "
+                         f"{n_om} frequencies) in {dt2:.1f} s, scaled x{scale:.0f} to the {T_pairs} pairs of a q-point"}
+        log(f"cpu oracle: {dt2:.1f} s for {o2 * m2} pairs -> {dt2 * scale:.0f} s/q-point extrapolated")
         del U_h
 
     out = {

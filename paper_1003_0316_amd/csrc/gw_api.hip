@@ -40,7 +40,7 @@ int default_chunk_pairs(const gw_pol_desc& d) {
     size_t p = target / ((size_t)d.N * 16);
     return (int)std::max<size_t>(64, std::min<size_t>(p, 65536));
   }
-  return mfma_default_chunk_pairs(d.N, d.precision);
+  return mfma_default_chunk_pairs(d.N, d.R, d.n_omega, d.precision);
 }
 
 Plan make_plan(const gw_pol_desc& d) {

@@ -988,7 +988,11 @@ int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32
 // Pairs per chunk: a multiple of the 128-pair tile width, at most 8192 and
 // with the c64 M chunk under 256 MB (it is re-read by the accumulation), chosen
 // so that the projection's workgroups fill whole rounds of the 256 CUs.
-int mfma_default_chunk_pairs(int N, int precision) {
+int g_bf16_pipeline = 2;
+int g_gemm_staging = 1;
+
+int mfma_default_chunk_pairs(int N, int R, int n_omega, int precision) {
+  if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_default_chunk_pairs(N, R, n_omega);
   const int tile_rows = (precision == GW_SPLIT_BF16 && g_proj_variant == 2 && N >= kLargeTileN) ? BM2 : BM;
   const long rows = (N + tile_rows - 1) / tile_rows;
   const long cap = std::max<long>(1, std::min<long>(64, (256L << 20) / ((long)N * 8 * BN)));
@@ -1013,13 +1017,13 @@ static size_t split_u_bytes(int precision, int N, int R) {
 }
 
 size_t mfma_pol_workspace(int precision, int N, int R, int tc, int n_omega) {
+  if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_pol_workspace(N, R, tc, n_omega);
   return split_u_bytes(precision, N, R) + align_up((size_t)N * tc * sizeof(float2)) +
          align_up((size_t)n_omega * tc * sizeof(float));
 }
 
 size_t mfma_project_workspace(int precision, int N, int R, int n_occ, int n_unocc) {
-  (void)n_occ;
-  (void)n_unocc;
+  if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_project_workspace(N, R, n_occ * n_unocc);
   return split_u_bytes(precision, N, R);
 }
 
@@ -1032,6 +1036,9 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
     return launch_project_f32(s, N, R, static_cast<const float2*>(U), static_cast<const float2*>(psi_occ),
                               static_cast<const float2*>(psi_unocc), n_unocc, 0, n_occ * n_unocc,
                               static_cast<float2*>(M), (long)n_occ * n_unocc);
+  if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2)
+    return tiled_project(s, N, R, n_occ, n_unocc, static_cast<const float2*>(U), static_cast<const float2*>(psi_occ),
+                         static_cast<const float2*>(psi_unocc), static_cast<float2*>(M), ws);
   const int word = word_of(precision);
   const int Rp = round_up(R, KS);
   Carver cv(ws);
@@ -1061,6 +1068,7 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
 
 int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
                       const OmegaList& om, void* ws) {
+  if (d.precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_polarization(s, d, chunks, tc, om, ws);
   Carver cv(ws);
   const int Rp = round_up(d.R, KS);
   uint32_t* Uh = nullptr;
@@ -1120,6 +1128,16 @@ extern "C" int gw_set_tuning(const char* key, int value) {
   if (k == "projection_variant") {
     if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: projection_variant is 1 or 2");
     gw::g_proj_variant = value;
+    return GW_OK;
+  }
+  if (k == "gemm_staging") {
+    if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: gemm_staging is 1 or 2");
+    gw::g_gemm_staging = value;
+    return GW_OK;
+  }
+  if (k == "bf16_pipeline") {
+    if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: bf16_pipeline is 1 or 2");
+    gw::g_bf16_pipeline = value;
     return GW_OK;
   }
   return gw::fail(GW_ERR_INVALID_ARG, std::string("gw_set_tuning: unknown key ") + key);

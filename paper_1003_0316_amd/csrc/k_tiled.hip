@@ -1,0 +1,750 @@
+// Split-BF16 path on pre-tiled operands.
+//
+// The two contractions of the method,
+//   projection    (Eq. proj_MB)   M[I][t]   = sum_r U[I][r] F_t(r),
+//                                 F_t(r)    = conj(psi_n(r)) psi_n'(r),
+//   accumulation  (Eq. polar_MB)  P_j[I][J] += sum_t w_j(t) M[I][t] conj(M[J][t]),
+// run on one GEMM core whose operands are prepared by streaming kernels in
+// the exact layout the core copies into LDS: bf16 hi/lo words (x = hi + lo),
+// complex values interleaved (re in the low half of a dword, im in the high
+// half), and every complex sign/permutation pattern the MFMA embedding needs
+// already applied.  The core then only moves contiguous 16-byte vectors and
+// issues MFMAs.
+//
+// Complex products as real MFMAs: with the reduction index carrying (re, im)
+// pairs, sum_k a_k b_k over interleaved rows gives
+//   [re(a), -im(a)] . [re(b), im(b)] = Re(a b)          (A word: conj a)
+//   [im(a),  re(a)] . [re(b), im(b)] = Im(a b)          (A word: swap a)
+// and for the accumulation, with X = s M and s_j(t) = sqrt(-w_j(t)) (the
+// weights are negative for every occupied-unoccupied pair of an insulator),
+// P_j -= X X^H:
+//   [re x_I, im x_I] . [re x_J, im x_J]   = Re(x_I conj x_J)   (A word: x)
+//   [im x_I, -re x_I] . [re x_J, im x_J]  = Im(x_I conj x_J)   (A word: -i x)
+// Each real product is split as hi*hi + hi*lo + lo*hi with FP32 accumulation.
+//
+// Tiled operand layout ("block-stage" = 128 rows x 16 complex k):
+//   dword index inside one word of a block-stage:
+//     ((s * 2 + h) * 128 + row) * 4 + j,   k = 8 s + 4 h + j
+//   i.e. the 32x32x16 MFMA fragment of lane (row = l % 32, h = l / 32) for
+//   step s is one aligned 16-byte vector, and 32 consecutive rows are 512
+//   contiguous bytes (LDS reads without bank conflicts).
+//   A-side arrays hold 4 words per block-stage (conj|swap or x|-ix, each
+//   hi then lo); B-side arrays hold hi, lo (the product array) or the same
+//   4-word array with only its first two words read.
+#include "gw_mfma.hpp"
+
+#include <algorithm>
+
+namespace gw {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TR = 128;               // rows per operand block
+constexpr int TK = 16;                // complex k per stage
+constexpr int WD = TR * TK;           // dwords per word per block-stage (2048 = 8 KB)
+constexpr int GT = 256;               // GEMM workgroup: 4 waves, 2 (rows) x 2 (cols)
+constexpr int TM = 128, TN = 256;     // GEMM output tile (rows from A, cols from B)
+constexpr int LDS_STAGE = 8 * WD;     // dwords per LDS stage: A 4 words + B 2 halves x 2 words
+constexpr size_t kGemmLds = 2 * LDS_STAGE * sizeof(uint32_t);   // double-buffered, 128 KB
+
+__device__ inline uint32_t pack_bf16(float a, float b) {
+  bf16x2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+// x = hi + lo with hi = bf16(x) (round to nearest even) and lo = bf16(x - hi).
+__device__ inline void split2(float x, float& h, float& l) {
+  h = (float)(__bf16)x;
+  l = x - h;
+}
+__device__ inline int lane_off(int sh, int row) { return (sh * TR + row) * 4; }
+
+// ------------------------------------------------------------ operand tiling
+
+// U (c64 [N][R]) -> A-side words [nI][nst][4][WD]: conj(U) hi, lo, swap(U) hi, lo.
+// Rows >= N and k >= R are zero.
+__global__ void tile_u_kernel(int N, int R, int nI, int nst, const float2* __restrict__ U,
+                              uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nI * nst * 4 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % TR);
+    const int sh = (int)((e / TR) % 4);
+    const size_t bs = e / (4 * TR);             // block * nst + stage
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int I = blk * TR + row;
+    const int r0 = st * TK + sh * 4;
+    uint32_t w[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float2 x = make_float2(0.f, 0.f);
+      if (I < N && r0 + j < R) x = U[(size_t)I * R + r0 + j];
+      float rh, rl, ih, il;
+      split2(x.x, rh, rl);
+      split2(x.y, ih, il);
+      w[0][j] = pack_bf16(rh, -ih);
+      w[1][j] = pack_bf16(rl, -il);
+      w[2][j] = pack_bf16(ih, rh);
+      w[3][j] = pack_bf16(il, rl);
+    }
+    uint32_t* o = out + bs * 4 * WD + lane_off(sh, row);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<uint4*>(o + (size_t)q * WD) = make_uint4(w[q][0], w[q][1], w[q][2], w[q][3]);
+  }
+}
+
+// Pair products F_t = conj(psi_occ) psi_unocc of one chunk -> B-side words
+// [nT][nst][2][WD] (hi, lo); pairs t >= T and k >= R are zero.  Chunk pair t
+// is grid index g = tb + t: occupied row g / nu of po, unoccupied row g % nu of pu.
+__global__ void pair_product_kernel(int R, int nst, int nT, const float2* __restrict__ po,
+                                    const float2* __restrict__ pu, int nu, long tb, int T,
+                                    uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nT * nst * 4 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(e % TR);
+    const int sh = (int)((e / TR) % 4);
+    const size_t bs = e / (4 * TR);
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int t = blk * TR + col;
+    const int r0 = st * TK + sh * 4;
+    uint32_t hw[4], lw[4];
+    const float2* a = nullptr;
+    const float2* b = nullptr;
+    if (t < T) {
+      const long g = tb + t;
+      a = po + (size_t)(g / nu) * R;
+      b = pu + (size_t)(g % nu) * R;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float fr = 0.f, fi = 0.f;
+      if (a && r0 + j < R) {
+        const float2 x = a[r0 + j], y = b[r0 + j];
+        fr = x.x * y.x + x.y * y.y;
+        fi = x.x * y.y - x.y * y.x;
+      }
+      float rh, rl, ih, il;
+      split2(fr, rh, rl);
+      split2(fi, ih, il);
+      hw[j] = pack_bf16(rh, ih);
+      lw[j] = pack_bf16(rl, il);
+    }
+    uint32_t* o = out + bs * 2 * WD + lane_off(sh, col);
+    *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    *reinterpret_cast<uint4*>(o + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+  }
+}
+
+// s_j(t) = sqrt(-w_j(t)), w_j(t) = 4 D / (D^2 + omega_j^2), D = eps_n - eps_n' < 0
+// (FP64, Eq. polar_MB weights), zero for the padding pairs t in [T, Tp).
+__global__ void weights_sqrt_kernel(const double* __restrict__ eps, int n_bands, int n_occ, Chunk c, OmegaList om,
+                                    int Tp, float* __restrict__ sw) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Tp) return;
+  double d = 0.0;
+  if (t < c.T) {
+    const long g = c.tb + t;
+    const int n = c.n0 + (int)(g / c.nu);
+    const int u = c.u0 + (int)(g % c.nu);
+    d = eps[(size_t)c.k * n_bands + n] - eps[(size_t)c.kq * n_bands + n_occ + u];
+  }
+  for (int j = 0; j < om.n; ++j) {
+    const double w = t < c.T ? 4.0 * d / (d * d + om.w[j] * om.w[j]) : 0.0;
+    sw[(size_t)j * Tp + t] = (float)sqrt(fmax(-w, 0.0));
+  }
+}
+
+// M (tiled complex FP32 [nI][nstT][4][TR][4], written by the projection) ->
+// X_j = s_j M as A-side words [n_omega][nIe][nstT][4][WD]: x hi, lo, (-i x) hi, lo.
+// Blocks in [nI, nIe) are zero.
+__global__ void scale_split_kernel(int nI, int nIe, int nstT, int Tp, int n_omega, const float2* __restrict__ Mt,
+                                   const float* __restrict__ sw, uint32_t* __restrict__ X) {
+  const size_t total = (size_t)nIe * nstT * 4 * TR;
+  const size_t xstride = (size_t)nIe * nstT * 4 * WD;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % TR);
+    const int sh = (int)((e / TR) % 4);
+    const size_t bs = e / (4 * TR);
+    const int st = (int)(bs % nstT), blk = (int)(bs / nstT);
+    float2 m[4];
+    if (blk < nI) {
+      const float4* src = reinterpret_cast<const float4*>(Mt + e * 4);
+      const float4 p = src[0], q = src[1];
+      m[0] = make_float2(p.x, p.y);
+      m[1] = make_float2(p.z, p.w);
+      m[2] = make_float2(q.x, q.y);
+      m[3] = make_float2(q.z, q.w);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) m[j] = make_float2(0.f, 0.f);
+    }
+    const int t0 = st * TK + sh * 4;
+    uint32_t* o = X + bs * 4 * WD + lane_off(sh, row);
+    for (int jw = 0; jw < n_omega; ++jw) {
+      const float4 s4 = *reinterpret_cast<const float4*>(sw + (size_t)jw * Tp + t0);
+      const float s[4] = {s4.x, s4.y, s4.z, s4.w};
+      uint32_t w[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float rh, rl, ih, il;
+        split2(s[j] * m[j].x, rh, rl);
+        split2(s[j] * m[j].y, ih, il);
+        w[0][j] = pack_bf16(rh, ih);
+        w[1][j] = pack_bf16(rl, il);
+        w[2][j] = pack_bf16(ih, -rh);
+        w[3][j] = pack_bf16(il, -rl);
+      }
+      uint32_t* oj = o + (size_t)jw * xstride;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        *reinterpret_cast<uint4*>(oj + (size_t)q * WD) = make_uint4(w[q][0], w[q][1], w[q][2], w[q][3]);
+    }
+  }
+}
+
+// --------------------------------------------------------------- GEMM core
+
+// Workgroups are handed to the 8 XCDs round-robin by linear id; renumber them
+// so that each XCD works through one contiguous range of tiles (neighbouring
+// tiles share operand blocks in that XCD's L2).
+__device__ inline int xcd_remap(int L, int G) {
+  const int base = G / 8, rem = G % 8;
+  const int x = L % 8, local = L / 8;
+  return x < rem ? x * (base + 1) + local : rem * (base + 1) + (x - rem) * base + local;
+}
+
+// Lower tiles (128-row block ti, 256-col block bj, ti >= 2 bj) in groups of
+// eight row blocks, column block by column block inside a group.
+__device__ inline void lower_tile_grouped(int l, int nI, int& ti, int& bj) {
+  for (int t0 = 0; t0 < nI; t0 += 8) {
+    const int t1 = min(t0 + 8, nI);
+    const int bjmax = (t1 - 1) / 2;
+    for (int b = 0; b <= bjmax; ++b) {
+      const int lo = max(t0, 2 * b);
+      const int cnt = t1 - lo;
+      if (l < cnt) {
+        ti = lo + l;
+        bj = b;
+        return;
+      }
+      l -= cnt;
+    }
+  }
+  ti = 0;
+  bj = 0;
+}
+
+enum GemmOut { OUT_TILED = 0, OUT_ROWS = 1, OUT_HERK = 2 };
+
+struct GemmArgs {
+  const uint32_t* A;   // A-side words, 4 per block-stage
+  const uint32_t* B;   // B-side words, first two of b_words per block-stage
+  int b_words;
+  size_t a_bstride;    // dwords between consecutive row blocks of A
+  size_t b_bstride;    // dwords between consecutive column blocks of B
+  int nst;             // stages (K / 16)
+  size_t omega_stride; // dwords between frequencies of A and B (accumulation)
+  int nI;              // row blocks of A
+  int nTj;             // 256-col tiles (projection)
+  int n_tiles;         // lower tiles per frequency (accumulation)
+  int N, T;            // valid rows / cols
+  float2* M;           // OUT_TILED: [nI][nst_out][4][TR][4]; OUT_ROWS: [N][ldm]
+  long ldm;
+  int nst_out;
+  double2* P;          // OUT_HERK: n_omega x [N][N]
+};
+
+__device__ inline floatx16 mma(uint4 a, uint4 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+// One stage of operands in flight through registers: A 32 KB, B two 16 KB
+// halves (named members: arrays of vectors here end up in scratch memory).
+struct Staged {
+  uint4 a0, a1, a2, a3, a4, a5, a6, a7, b0, b1, b2, b3, c0, c1, c2, c3;
+};
+
+__device__ __forceinline__ uint4 ld16(const uint32_t* p, int q, int tid) {
+  return *reinterpret_cast<const uint4*>(p + (q * GT + tid) * 4);
+}
+__device__ __forceinline__ void st16(uint32_t* p, int q, int tid, uint4 v) {
+  *reinterpret_cast<uint4*>(p + (q * GT + tid) * 4) = v;
+}
+
+__device__ __forceinline__ void stage_load(Staged& r, const uint32_t* Ap, const uint32_t* B0, const uint32_t* B1,
+                                           size_t b_step, int st, int tid) {
+  const uint32_t* a = Ap + (size_t)st * 4 * WD;
+  const uint32_t* b0 = B0 + (size_t)st * b_step;
+  const uint32_t* b1 = B1 + (size_t)st * b_step;
+  r.a0 = ld16(a, 0, tid); r.a1 = ld16(a, 1, tid); r.a2 = ld16(a, 2, tid); r.a3 = ld16(a, 3, tid);
+  r.a4 = ld16(a, 4, tid); r.a5 = ld16(a, 5, tid); r.a6 = ld16(a, 6, tid); r.a7 = ld16(a, 7, tid);
+  r.b0 = ld16(b0, 0, tid); r.b1 = ld16(b0, 1, tid); r.b2 = ld16(b0, 2, tid); r.b3 = ld16(b0, 3, tid);
+  r.c0 = ld16(b1, 0, tid); r.c1 = ld16(b1, 1, tid); r.c2 = ld16(b1, 2, tid); r.c3 = ld16(b1, 3, tid);
+}
+
+// LDS stage: A words at [0, 4 WD), B half c word q at 4 WD + (2 c + q) WD.
+// part 0 stores A, part 1 stores B.
+__device__ __forceinline__ void stage_store(const Staged& r, uint32_t* L, int part, int tid) {
+  if (part == 0) {
+    st16(L, 0, tid, r.a0); st16(L, 1, tid, r.a1); st16(L, 2, tid, r.a2); st16(L, 3, tid, r.a3);
+    st16(L, 4, tid, r.a4); st16(L, 5, tid, r.a5); st16(L, 6, tid, r.a6); st16(L, 7, tid, r.a7);
+  } else {
+    uint32_t* b0 = L + 4 * WD;
+    uint32_t* b1 = L + 6 * WD;
+    st16(b0, 0, tid, r.b0); st16(b0, 1, tid, r.b1); st16(b0, 2, tid, r.b2); st16(b0, 3, tid, r.b3);
+    st16(b1, 0, tid, r.c0); st16(b1, 1, tid, r.c1); st16(b1, 2, tid, r.c2); st16(b1, 3, tid, r.c3);
+  }
+}
+
+struct Frags {
+  uint4 a[4][2];   // A words (conj|x hi, lo, swap|-ix hi, lo) x row blocks
+  uint4 b[2][4];   // B words (hi, lo) x column blocks
+};
+
+__device__ __forceinline__ void read_frags(Frags& f, const uint32_t* L, int s, int wm, int wn, int l32, int h) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+      f.a[q][rb] = *reinterpret_cast<const uint4*>(L + q * WD + lane_off(s * 2 + h, wm * 64 + rb * 32 + l32));
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      f.b[q][cb] = *reinterpret_cast<const uint4*>(L + (4 + 2 * wn + q) * WD + lane_off(s * 2 + h, cb * 32 + l32));
+}
+
+// 48 MFMAs: re += A0h Bh + A0h Bl + A0l Bh, im likewise with A1.
+__device__ __forceinline__ void mma_step(const Frags& f, floatx16 (&cr)[2][4], floatx16 (&ci)[2][4]) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      cr[rb][cb] = mma(f.a[0][rb], f.b[0][cb], cr[rb][cb]);
+      ci[rb][cb] = mma(f.a[2][rb], f.b[0][cb], ci[rb][cb]);
+      cr[rb][cb] = mma(f.a[0][rb], f.b[1][cb], cr[rb][cb]);
+      ci[rb][cb] = mma(f.a[2][rb], f.b[1][cb], ci[rb][cb]);
+      cr[rb][cb] = mma(f.a[1][rb], f.b[0][cb], cr[rb][cb]);
+      ci[rb][cb] = mma(f.a[3][rb], f.b[0][cb], ci[rb][cb]);
+    }
+}
+
+// The 24 MFMAs of mma_step for row block rb.
+__device__ __forceinline__ void mma_half(const Frags& f, int rb, floatx16 (&cr)[2][4], floatx16 (&ci)[2][4]) {
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    cr[rb][cb] = mma(f.a[0][rb], f.b[0][cb], cr[rb][cb]);
+    ci[rb][cb] = mma(f.a[2][rb], f.b[0][cb], ci[rb][cb]);
+    cr[rb][cb] = mma(f.a[0][rb], f.b[1][cb], cr[rb][cb]);
+    ci[rb][cb] = mma(f.a[2][rb], f.b[1][cb], ci[rb][cb]);
+    cr[rb][cb] = mma(f.a[1][rb], f.b[0][cb], cr[rb][cb]);
+    ci[rb][cb] = mma(f.a[3][rb], f.b[0][cb], ci[rb][cb]);
+  }
+}
+
+// Scheduling-group masks (LLVM AMDGPU): MFMA, global load, LDS read, LDS write.
+constexpr int SG_MFMA = 0x008, SG_VMR = 0x020, SG_DSR = 0x100, SG_DSW = 0x200;
+
+// Workgroup barrier ordering LDS only (global loads in flight stay in flight).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One K stage (two MFMA steps of 8 complex k) from LDS buffer st % 2; r holds
+// stage st + 1 on entry and stage st + 2 on exit.  The order is pinned:
+//   fragments of step 0;
+//   step 0 MFMAs with r written to the idle buffer and the fragments of
+//   step 1 read between them;
+//   global loads of stage st + 2 into r, then step 1 MFMAs.
+__device__ __forceinline__ void mma_stage(uint32_t* lds, int st, Staged& r, const uint32_t* Ap, const uint32_t* B0,
+                                          const uint32_t* B1, size_t b_step, int nst, int tid, int wm, int wn,
+                                          int l32, int h, floatx16 (&cr)[2][4], floatx16 (&ci)[2][4]) {
+  const uint32_t* L = lds + (st & 1) * LDS_STAGE;
+  uint32_t* Ln = lds + ((st + 1) & 1) * LDS_STAGE;
+  Frags f0, f1;
+  read_frags(f0, L, 0, wm, wn, l32, h);
+  __builtin_amdgcn_sched_barrier(0);
+  stage_store(r, Ln, 0, tid);
+  stage_store(r, Ln, 1, tid);
+  read_frags(f1, L, 1, wm, wn, l32, h);
+  mma_step(f0, cr, ci);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(SG_DSW, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(SG_DSR, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 1, 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  stage_load(r, Ap, B0, B1, b_step, min(st + 2, nst - 1), tid);
+  mma_step(f1, cr, ci);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    __builtin_amdgcn_sched_group_barrier(SG_VMR, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, 3, 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Direct global -> LDS copy of one stage (global_load_lds_dwordx4): lane i of
+// a wave writes the 16 bytes at the wave's (uniform) LDS address + 16 i, so
+// the tiled operand image lands in LDS exactly as it lies in memory.
+__device__ __forceinline__ void stage_dma(uint32_t* Ln, const uint32_t* Ap, const uint32_t* B0, const uint32_t* B1,
+                                          size_t b_step, int st, int tid, int w) {
+  const uint32_t* a = Ap + (size_t)st * 4 * WD;
+  const uint32_t* b0 = B0 + (size_t)st * b_step;
+  const uint32_t* b1 = B1 + (size_t)st * b_step;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    __builtin_amdgcn_global_load_lds(a + (q * GT + tid) * 4, (lds_void*)(Ln + (q * GT + w * 64) * 4), 16, 0, 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    __builtin_amdgcn_global_load_lds(b0 + (q * GT + tid) * 4, (lds_void*)(Ln + 4 * WD + (q * GT + w * 64) * 4), 16,
+                                     0, 0);
+    __builtin_amdgcn_global_load_lds(b1 + (q * GT + tid) * 4, (lds_void*)(Ln + 6 * WD + (q * GT + w * 64) * 4), 16,
+                                     0, 0);
+  }
+}
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima).
+__device__ __forceinline__ void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// One K stage with direct-to-LDS staging: all fragments of the stage are
+// read first (a copy into LDS makes every later LDS read wait for it), the
+// first 24 MFMAs start, then the copy of stage st + 1 into the idle buffer
+// is issued and has the remaining 72 MFMAs to land.
+__device__ __forceinline__ void mma_stage_dma(uint32_t* lds, int st, const uint32_t* Ap, const uint32_t* B0,
+                                              const uint32_t* B1, size_t b_step, int nst, int tid, int w, int wm,
+                                              int wn, int l32, int h, floatx16 (&cr)[2][4], floatx16 (&ci)[2][4]) {
+  const uint32_t* L = lds + (st & 1) * LDS_STAGE;
+  uint32_t* Ln = lds + ((st + 1) & 1) * LDS_STAGE;
+  Frags f0, f1;
+  read_frags(f0, L, 0, wm, wn, l32, h);
+  read_frags(f1, L, 1, wm, wn, l32, h);
+  mma_half(f0, 0, cr, ci);
+  __builtin_amdgcn_sched_barrier(0);
+  if (st + 1 < nst) stage_dma(Ln, Ap, B0, B1, b_step, st + 1, tid, w);
+  __builtin_amdgcn_sched_barrier(0);
+  mma_half(f0, 1, cr, ci);
+  mma_step(f1, cr, ci);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int OUT, int DMA>
+__global__ __launch_bounds__(GT, 1) void gemm_bf16x3_kernel(GemmArgs g) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  const int V = xcd_remap(blockIdx.x, gridDim.x);
+  int ti, tj, jw = 0;
+  if constexpr (OUT == OUT_HERK) {
+    jw = V / g.n_tiles;
+    lower_tile_grouped(V % g.n_tiles, g.nI, ti, tj);
+  } else {
+    const int per = 8 * g.nTj;
+    const int grp = V / per, within = V % per;
+    const int gsz = min(8, g.nI - grp * 8);
+    tj = within / gsz;
+    ti = grp * 8 + within % gsz;
+  }
+  const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
+  const uint32_t* B0 = g.B + jw * g.omega_stride + (size_t)(2 * tj) * g.b_bstride;
+  const uint32_t* B1 = B0 + g.b_bstride;
+  const size_t b_step = (size_t)g.b_words * WD;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w >> 1, wn = w & 1;
+  const int l32 = lane & 31, h = lane >> 5;
+
+  floatx16 cr[2][4], ci[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        cr[a][b][v] = 0.f;
+        ci[a][b][v] = 0.f;
+      }
+
+  if constexpr (DMA) {
+    stage_dma(lds, Ap, B0, B1, b_step, 0, tid, w);
+    wait_vm0();
+    lds_barrier();
+    for (int st = 0; st < g.nst; ++st) {
+      mma_stage_dma(lds, st, Ap, B0, B1, b_step, g.nst, tid, w, wm, wn, l32, h, cr, ci);
+      wait_vm0();
+      lds_barrier();
+    }
+  } else {
+    // The staged registers hold the next stage while the current one is
+    // multiplied from LDS; they are written to the idle buffer early in the
+    // iteration and then receive the stage after next, so each global load
+    // has about one iteration to arrive.
+    Staged r;
+    stage_load(r, Ap, B0, B1, b_step, 0, tid);
+    stage_store(r, lds, 0, tid);
+    stage_store(r, lds, 1, tid);
+    stage_load(r, Ap, B0, B1, b_step, min(1, g.nst - 1), tid);
+    lds_barrier();
+    // (past the end, loads repeat the final stage, in bounds, and stores fill
+    // the idle buffer, which is never read)
+    for (int st = 0; st < g.nst; ++st) {
+      mma_stage(lds, st, r, Ap, B0, B1, b_step, g.nst, tid, wm, wn, l32, h, cr, ci);
+      lds_barrier();
+    }
+  }
+
+  if constexpr (OUT == OUT_HERK) {
+    // P_j -= C over the lower triangle in FP64.  The FP32 tile goes through
+    // LDS in two 128-column halves so that the read-modify-write of P runs
+    // as a short loop over coalesced rows (FP64 conversions of the whole
+    // register tile at once would not fit in registers).
+    float2* E = reinterpret_cast<float2*>(lds);   // [128][128]
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (wn == c) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+              E[row * 128 + cb * 32 + l32] = make_float2(cr[rb][cb][v], ci[rb][cb][v]);
+            }
+      }
+      __syncthreads();
+      double2* Pj = g.P + (size_t)jw * g.N * g.N;
+#pragma unroll 4
+      for (int e = tid; e < 128 * 128; e += GT) {
+        const int gi = ti * TM + (e >> 7), gj = tj * TN + c * 128 + (e & 127);
+        if (gi < g.N && gj <= gi) {
+          const float2 x = E[e];
+          double2* p = Pj + (size_t)gi * g.N + gj;
+          double2 y = *p;
+          y.x -= (double)x.x;
+          y.y -= (double)x.y;
+          *p = y;
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  // epilogue: element (row, col) of block (rb, cb), register v
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * 128 + cb * 32 + l32;
+        const float re = cr[rb][cb][v], im = ci[rb][cb][v];
+        if constexpr (OUT == OUT_TILED) {
+          const int t = tj * TN + col;
+          const size_t bs = (size_t)ti * g.nst_out + t / TK;
+          const int kk = t % TK;
+          g.M[(bs * 4 + (kk >> 2)) * TR * 4 + row * 4 + (kk & 3)] = make_float2(re, im);
+        } else {
+          const int gi = ti * TM + row, gt = tj * TN + col;
+          if (gi < g.N && gt < g.T) g.M[(size_t)gi * g.ldm + gt] = make_float2(re, im);
+        }
+      }
+}
+
+template <int OUT, int DMA>
+int enable_gemm_lds() {
+  static int done = 0;
+  if (done) return GW_OK;
+  GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_bf16x3_kernel<OUT, DMA>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds));
+  done = 1;
+  return GW_OK;
+}
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+inline unsigned stream_blocks(size_t work) { return (unsigned)std::max<size_t>(1, std::min<size_t>((work + 255) / 256, 65536)); }
+
+int count_lower_tiles(int nI) {
+  int n = 0;
+  for (int ti = 0; ti < nI; ++ti) n += ti / 2 + 1;
+  return n;
+}
+
+// Sizes of one call's arrays (elements).
+struct TiledDims {
+  int nI, nIe, nstR, Tp, nT, nstT;
+  size_t u_words, q_words, m_c64, x_words, sw_f32;
+  TiledDims(int N, int R, int T, int n_omega) {
+    nI = cdiv(N, TR);
+    nIe = (nI + 1) & ~1;
+    nstR = cdiv(R, TK);
+    Tp = cdiv(T, TN) * TN;
+    nT = Tp / TR;
+    nstT = Tp / TK;
+    u_words = (size_t)nI * nstR * 4 * WD;
+    q_words = (size_t)nT * nstR * 2 * WD;
+    m_c64 = (size_t)nI * nstT * WD;
+    x_words = (size_t)n_omega * nIe * nstT * 4 * WD;
+    sw_f32 = (size_t)n_omega * Tp;
+  }
+  size_t bytes() const {
+    return align_up(u_words * 4) + align_up(q_words * 4) + align_up(m_c64 * 8) + align_up(x_words * 4) +
+           align_up(sw_f32 * 4);
+  }
+};
+
+int launch_tile_u(hipStream_t s, const TiledDims& d, int N, int R, const float2* U, uint32_t* Uw) {
+  hipLaunchKernelGGL(tile_u_kernel, dim3(stream_blocks((size_t)d.nI * d.nstR * 4 * TR)), dim3(256), 0, s, N, R, d.nI,
+                     d.nstR, U, Uw);
+  GW_LAUNCHED("tile_u_kernel");
+  return GW_OK;
+}
+
+int launch_pair_product(hipStream_t s, const TiledDims& d, int R, const float2* po, const float2* pu, int nu, long tb,
+                        int T, uint32_t* Q) {
+  ProfScope prof(s, "pair_product_kernel");
+  hipLaunchKernelGGL(pair_product_kernel, dim3(stream_blocks((size_t)d.nT * d.nstR * 4 * TR)), dim3(256), 0, s, R,
+                     d.nstR, d.nT, po, pu, nu, tb, T, Q);
+  GW_LAUNCHED("pair_product_kernel");
+  return GW_OK;
+}
+
+template <int OUT, int DMA>
+int launch_gemm_as(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
+  int st = enable_gemm_lds<OUT, DMA>();
+  if (st != GW_OK) return st;
+  ProfScope prof(s, name);
+  hipLaunchKernelGGL((gemm_bf16x3_kernel<OUT, DMA>), dim3(grid), dim3(GT), kGemmLds, s, a);
+  GW_LAUNCHED("gemm_bf16x3_kernel");
+  return GW_OK;
+}
+
+template <int OUT>
+int launch_gemm(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
+  return g_gemm_staging == 2 ? launch_gemm_as<OUT, 1>(s, a, grid, name) : launch_gemm_as<OUT, 0>(s, a, grid, name);
+}
+
+}  // namespace
+
+size_t tiled_pol_workspace(int N, int R, int tc, int n_omega) { return TiledDims(N, R, tc, n_omega).bytes(); }
+
+size_t tiled_project_workspace(int N, int R, int T) { return TiledDims(N, R, T, 0).bytes(); }
+
+int tiled_default_chunk_pairs(int N, int R, int n_omega) {
+  // Whole 256-pair tiles.  The projection grid (row blocks x pair tiles)
+  // should fill complete rounds of the 256 compute units; the accumulation
+  // adds each chunk into the FP64 P once, so longer chunks amortise that
+  // read-modify-write; the chunk's arrays (products, scaled copies per
+  // frequency) stay within 16 GB.
+  const long rows = cdiv(N, TR);
+  const long nIe = (rows + 1) & ~1L;
+  const size_t per_tile = (size_t)TN * ((size_t)cdiv(R, TK) * TK * 8 + (size_t)n_omega * nIe * TR * 16);
+  const long cap = std::max<long>(1, std::min<long>(32, (long)(((size_t)16 << 30) / per_tile)));
+  long best_x = 1;
+  double best = -1.0;
+  for (long x = 1; x <= cap; ++x) {
+    const long wg = rows * x;
+    const double fill = (double)wg / (double)(((wg + 255) / 256) * 256);
+    if (fill > best + 0.005 || (fill > best - 0.005 && x > best_x)) {
+      best = std::max(best, fill);
+      best_x = x;
+    }
+  }
+  return (int)(best_x * TN);
+}
+
+int tiled_project(hipStream_t s, int N, int R, int n_occ, int n_unocc, const float2* U, const float2* po,
+                  const float2* pu, float2* M, void* ws) {
+  const int T = n_occ * n_unocc;
+  TiledDims d(N, R, T, 0);
+  Carver cv(ws);
+  uint32_t* Uw = cv.take<uint32_t>(d.u_words);
+  uint32_t* Q = cv.take<uint32_t>(d.q_words);
+  int st;
+  if ((st = launch_tile_u(s, d, N, R, U, Uw)) != GW_OK) return st;
+  if ((st = launch_pair_product(s, d, R, po, pu, n_unocc, 0, T, Q)) != GW_OK) return st;
+  GemmArgs a{};
+  a.A = Uw;
+  a.B = Q;
+  a.b_words = 2;
+  a.nst = d.nstR;
+  a.a_bstride = (size_t)d.nstR * 4 * WD;
+  a.b_bstride = (size_t)d.nstR * 2 * WD;
+  a.nI = d.nI;
+  a.nTj = d.Tp / TN;
+  a.N = N;
+  a.T = T;
+  a.M = M;
+  a.ldm = T;
+  return launch_gemm<OUT_ROWS>(s, a, d.nI * a.nTj, "project_bf16_kernel");
+}
+
+int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
+                       const OmegaList& om, void* ws) {
+  TiledDims dm(d.N, d.R, tc, d.n_omega);
+  Carver cv(ws);
+  uint32_t* Uw = cv.take<uint32_t>(dm.u_words);
+  uint32_t* Q = cv.take<uint32_t>(dm.q_words);
+  float2* Mt = cv.take<float2>(dm.m_c64);
+  uint32_t* X = cv.take<uint32_t>(dm.x_words);
+  float* sw = cv.take<float>(dm.sw_f32);
+  const float2* psi = static_cast<const float2*>(d.psi);
+  const int nb = d.n_occ + d.n_unocc;
+  int st;
+  if ((st = launch_tile_u(s, dm, d.N, d.R, static_cast<const float2*>(d.U), Uw)) != GW_OK) return st;
+  const int n_tiles = count_lower_tiles(dm.nI);
+  for (const Chunk& c : chunks) {
+    // the chunk arrays are sized for tc pairs; a shorter last chunk pads with zeros
+    TiledDims cd(d.N, d.R, c.T, d.n_omega);
+    const float2* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
+    const float2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
+    hipLaunchKernelGGL(weights_sqrt_kernel, dim3(cdiv(cd.Tp, 256)), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om, cd.Tp,
+                       sw);
+    GW_LAUNCHED("weights_sqrt_kernel");
+    if ((st = launch_pair_product(s, cd, d.R, po, pu, c.nu, c.tb, c.T, Q)) != GW_OK) return st;
+    GemmArgs a{};
+    a.A = Uw;
+    a.B = Q;
+    a.b_words = 2;
+    a.nst = cd.nstR;
+    a.a_bstride = (size_t)cd.nstR * 4 * WD;
+    a.b_bstride = (size_t)cd.nstR * 2 * WD;
+    a.nI = cd.nI;
+    a.nTj = cd.Tp / TN;
+    a.N = d.N;
+    a.T = c.T;
+    a.M = Mt;
+    a.nst_out = cd.nstT;
+    if ((st = launch_gemm<OUT_TILED>(s, a, cd.nI * a.nTj, "project_bf16_kernel")) != GW_OK) return st;
+    {
+      ProfScope prof(s, "scale_split_kernel");
+      hipLaunchKernelGGL(scale_split_kernel, dim3(stream_blocks((size_t)cd.nIe * cd.nstT * 4 * TR)), dim3(256), 0, s,
+                         cd.nI, cd.nIe, cd.nstT, cd.Tp, d.n_omega, Mt, sw, X);
+      GW_LAUNCHED("scale_split_kernel");
+    }
+    GemmArgs b{};
+    b.A = X;
+    b.B = X;
+    b.b_words = 4;
+    b.nst = cd.nstT;
+    b.a_bstride = (size_t)cd.nstT * 4 * WD;
+    b.b_bstride = (size_t)cd.nstT * 4 * WD;
+    b.omega_stride = (size_t)cd.nIe * cd.nstT * 4 * WD;
+    b.nI = cd.nI;
+    b.n_tiles = n_tiles;
+    b.N = d.N;
+    b.P = reinterpret_cast<double2*>(d.P);
+    if ((st = launch_gemm<OUT_HERK>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")) != GW_OK) return st;
+  }
+  return GW_OK;
+}
+
+}  // namespace gw

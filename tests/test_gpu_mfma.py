@@ -132,23 +132,33 @@ def test_poisoned_workspace(lib, prec):
     assert torch.equal(P1, P2)
 
 
-@pytest.mark.parametrize("pv", [1, 2])
-def test_split_bf16_kernel_variants(lib, pv):
-    """Every tile variant of the split-BF16 projection meets the same bar (N
-    spans two 256-row tiles with a ragged tail; R and the pair count are
-    ragged)."""
+@pytest.mark.parametrize("pipeline,pv,staging", [(1, 1, 1), (1, 2, 1), (2, 2, 1), (2, 2, 2)])
+def test_split_bf16_kernel_variants(lib, pipeline, pv, staging):
+    """Every kernel variant of the split-BF16 path meets the same bar (N spans
+    two 256-row tiles with a ragged tail; R and the pair count are ragged):
+    operands staged inside the GEMM kernels with either projection tiling, and
+    pre-tiled operands on the shared GEMM core, staged through registers or
+    copied straight into LDS."""
     import torch
     shape = dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150)
     inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=9, omega=gwsynth.omega_mesh("m16"))
     U, psi = _dev(inp)
     try:
+        lib.gw_set_tuning("bf16_pipeline", pipeline)
         lib.gw_set_tuning("projection_variant", pv)
+        lib.gw_set_tuning("gemm_staging", staging)
         P = lib.gw_polarization(U, psi, inp.eps, inp.omega, 3, precision="split_bf16", kq=inp.kq)
+        M = lib.gw_project(U, psi[0, :3].contiguous(), psi[0, 3:].contiguous(), "split_bf16")
         torch.cuda.synchronize()
     finally:
+        lib.gw_set_tuning("bf16_pipeline", 2)
         lib.gw_set_tuning("projection_variant", 2)
+        lib.gw_set_tuning("gemm_staging", 1)
     Ur, pr = _rounded(inp)
     ref = orc.polarization(Ur, pr, inp.eps, inp.omega, 3, kq=inp.kq)
     err = orc.rel_fro(P.cpu().numpy(), ref)
-    print(f"projection variant {pv}: max rel err {err.max():.2e}")
+    Mref = orc.projections(Ur, pr[0, :3], pr[0, 3:])
+    merr = np.linalg.norm(M.cpu().numpy() - Mref) / np.linalg.norm(Mref)
+    print(f"pipeline {pipeline} projection variant {pv} staging {staging}: P max rel err {err.max():.2e}, M rel err {merr:.2e}")
     assert err.max() < TOL
+    assert merr < 1e-5
