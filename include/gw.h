@@ -231,13 +231,25 @@ int gw_surrogate_judge(void* stream, const gw_surr_desc* d_host, const float* Y,
                        size_t ws_bytes);
 
 /* --------------------------------------------------------------------- tuning
- * Process-wide kernel-variant switches (all results stay within the same
- * tolerances; the work done is identical).  Keys:
- *   "projection_variant"  split-BF16 projection for N >= 256:
- *                         1: 128 x 128 output tiles;
- *                         2 (default): 256 x 128 output tiles with the staging
- *                         of the next K stage interleaved with the MFMAs.
- * Values out of range and unknown keys give GW_ERR_INVALID_ARG. */
+ * Process-wide kernel-variant switches for the split-BF16 path (all results
+ * stay within the same tolerances; the work done is identical).  Keys:
+ *   "bf16_pipeline"       1: pair products (Eq. proj_MB) formed and split in
+ *                         registers while the projection kernel stages its
+ *                         tiles, weights applied while the accumulation
+ *                         kernel stages its tiles;
+ *                         2 (default): streaming kernels write the split,
+ *                         sign-patterned operand words (U once per call, the
+ *                         products and the weighted projections per chunk)
+ *                         in the tiled layout of one shared MFMA GEMM core.
+ *   "projection_variant"  pipeline 1 only, N >= 256: 1: 128 x 128 output
+ *                         tiles; 2 (default): 256 x 128 output tiles with the
+ *                         staging of the next K stage interleaved with the
+ *                         MFMAs.
+ *   "gemm_staging"        pipeline 2 only: 1 (default): operand stages pass
+ *                         through registers into LDS; 2: direct global-to-LDS
+ *                         copies.
+ * Values out of range and unknown keys give GW_ERR_INVALID_ARG.  Not
+ * thread-safe: set before launching work. */
 int gw_set_tuning(const char* key_host, int value);
 
 /* ------------------------------------------------------------------ profiling

@@ -144,3 +144,18 @@ def test_project_validation(b):
     assert L.gw_project(None, 0, 0, 4, 1, 1, fake, fake, fake, fake, None, 0) == -1
     assert L.gw_project(None, 9, 4, 4, 1, 1, fake, fake, fake, fake, None, 0) == -1
     assert L.gw_project(None, 0, 4, 4, 1, 1, None, fake, fake, fake, None, 0) == -1
+
+
+def test_tuning_switches_validate(b):
+    """gw_set_tuning accepts the documented keys and values only (host-side)."""
+    L = b.lib()
+    for key, lo, hi, default in (("bf16_pipeline", 1, 2, 2), ("projection_variant", 1, 2, 2),
+                                 ("gemm_staging", 1, 2, 1)):
+        for v in (lo, hi):
+            assert L.gw_set_tuning(key.encode(), v) == 0
+        for v in (lo - 1, hi + 1):
+            assert L.gw_set_tuning(key.encode(), v) == -1
+            assert key in L.gw_last_error().decode()
+        assert L.gw_set_tuning(key.encode(), default) == 0
+    assert L.gw_set_tuning(b"no_such_key", 1) == -1
+    assert L.gw_set_tuning(None, 1) == -1
