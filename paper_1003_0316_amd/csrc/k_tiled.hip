@@ -437,11 +437,12 @@ __device__ __forceinline__ void mma_stage_dma(uint32_t* lds, int st, const uint3
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int OUT, int DMA>
-__global__ __launch_bounds__(GT, 1) void gemm_bf16x3_kernel(GemmArgs g) {
-  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+// Output tile of this workgroup: row block ti (128 rows), column tile tj
+// (256 columns) and, for the accumulation, frequency jw.
+template <int OUT>
+__device__ __forceinline__ void decode_tile(const GemmArgs& g, int& ti, int& tj, int& jw) {
   const int V = xcd_remap(blockIdx.x, gridDim.x);
-  int ti, tj, jw = 0;
+  jw = 0;
   if constexpr (OUT == OUT_HERK) {
     jw = V / g.n_tiles;
     lower_tile_grouped(V % g.n_tiles, g.nI, ti, tj);
@@ -452,6 +453,13 @@ __global__ __launch_bounds__(GT, 1) void gemm_bf16x3_kernel(GemmArgs g) {
     tj = within / gsz;
     ti = grp * 8 + within % gsz;
   }
+}
+
+template <int OUT, int DMA>
+__global__ __launch_bounds__(GT, 1) void gemm_bf16x3_kernel(GemmArgs g) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  int ti, tj, jw;
+  decode_tile<OUT>(g, ti, tj, jw);
   const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
   const uint32_t* B0 = g.B + jw * g.omega_stride + (size_t)(2 * tj) * g.b_bstride;
   const uint32_t* B1 = B0 + g.b_bstride;
@@ -559,6 +567,167 @@ __global__ __launch_bounds__(GT, 1) void gemm_bf16x3_kernel(GemmArgs g) {
       }
 }
 
+// ---------------------------------------------- 8-wave variant of the core
+// Same tile (128 x 256), operands, LDS image and epilogues, with 8 waves (two
+// per SIMD) of 64 x 64 outputs each (128 accumulators per lane), so that one
+// wave's waits on LDS, barriers and loads overlap the other wave's MFMAs.
+constexpr int GT8 = 512;
+
+struct Staged8 {
+  uint4 a0, a1, a2, a3, b0, b1, c0, c1;
+};
+
+__device__ __forceinline__ void stage_load8(Staged8& r, const uint32_t* Ap, const uint32_t* B0, const uint32_t* B1,
+                                            size_t b_step, int st, int tid) {
+  const uint32_t* a = Ap + (size_t)st * 4 * WD;
+  const uint32_t* b0 = B0 + (size_t)st * b_step;
+  const uint32_t* b1 = B1 + (size_t)st * b_step;
+  auto ld = [&](const uint32_t* p, int q) __attribute__((always_inline)) {
+    return *reinterpret_cast<const uint4*>(p + (q * GT8 + tid) * 4);
+  };
+  r.a0 = ld(a, 0); r.a1 = ld(a, 1); r.a2 = ld(a, 2); r.a3 = ld(a, 3);
+  r.b0 = ld(b0, 0); r.b1 = ld(b0, 1); r.c0 = ld(b1, 0); r.c1 = ld(b1, 1);
+}
+
+__device__ __forceinline__ void stage_store8(const Staged8& r, uint32_t* L, int part, int tid) {
+  auto st = [&](uint32_t* p, int q, uint4 v) __attribute__((always_inline)) {
+    *reinterpret_cast<uint4*>(p + (q * GT8 + tid) * 4) = v;
+  };
+  if (part == 0) {
+    st(L, 0, r.a0); st(L, 1, r.a1); st(L, 2, r.a2); st(L, 3, r.a3);
+  } else {
+    st(L + 4 * WD, 0, r.b0); st(L + 4 * WD, 1, r.b1); st(L + 6 * WD, 0, r.c0); st(L + 6 * WD, 1, r.c1);
+  }
+}
+
+struct Frags8 {
+  uint4 a[4][2];
+  uint4 b[2][2];
+};
+
+template <int OUT>
+__global__ __launch_bounds__(GT8, 1) void gemm8_bf16x3_kernel(GemmArgs g) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  int ti, tj, jw;
+  decode_tile<OUT>(g, ti, tj, jw);
+  const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
+  const uint32_t* B0 = g.B + jw * g.omega_stride + (size_t)(2 * tj) * g.b_bstride;
+  const uint32_t* B1 = B0 + g.b_bstride;
+  const size_t b_step = (size_t)g.b_words * WD;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w >> 2, wn = w & 3;          // rows wm*64, columns wn*64
+  const int half = wn >> 1, c0 = (wn & 1) * 64;  // B half holding this wave's columns
+  const int l32 = lane & 31, h = lane >> 5;
+
+  floatx16 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        cr[a][b][v] = 0.f;
+        ci[a][b][v] = 0.f;
+      }
+
+  Staged8 r;
+  stage_load8(r, Ap, B0, B1, b_step, 0, tid);
+  stage_store8(r, lds, 0, tid);
+  stage_store8(r, lds, 1, tid);
+  stage_load8(r, Ap, B0, B1, b_step, min(1, g.nst - 1), tid);
+  lds_barrier();
+  for (int st = 0; st < g.nst; ++st) {
+    const uint32_t* L = lds + (st & 1) * LDS_STAGE;
+    uint32_t* Ln = lds + ((st + 1) & 1) * LDS_STAGE;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      Frags8 f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+          f.a[q][rb] = *reinterpret_cast<const uint4*>(L + q * WD + lane_off(s * 2 + h, wm * 64 + rb * 32 + l32));
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          f.b[q][cb] =
+              *reinterpret_cast<const uint4*>(L + (4 + 2 * half + q) * WD + lane_off(s * 2 + h, c0 + cb * 32 + l32));
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          cr[rb][cb] = mma(f.a[0][rb], f.b[0][cb], cr[rb][cb]);
+          ci[rb][cb] = mma(f.a[2][rb], f.b[0][cb], ci[rb][cb]);
+          cr[rb][cb] = mma(f.a[0][rb], f.b[1][cb], cr[rb][cb]);
+          ci[rb][cb] = mma(f.a[2][rb], f.b[1][cb], ci[rb][cb]);
+          cr[rb][cb] = mma(f.a[1][rb], f.b[0][cb], cr[rb][cb]);
+          ci[rb][cb] = mma(f.a[3][rb], f.b[0][cb], ci[rb][cb]);
+        }
+      // the staged next stage goes to the idle buffer, half per step; after
+      // the second half the registers take the stage after next (past the
+      // end: the final stage again, in bounds, into a buffer never read)
+      stage_store8(r, Ln, s, tid);
+      if (s == 1) stage_load8(r, Ap, B0, B1, b_step, min(st + 2, g.nst - 1), tid);
+    }
+    lds_barrier();
+  }
+
+  if constexpr (OUT == OUT_HERK) {
+    float2* E = reinterpret_cast<float2*>(lds);   // [128][128], one column half at a time
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (half == c) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+              E[row * 128 + c0 + cb * 32 + l32] = make_float2(cr[rb][cb][v], ci[rb][cb][v]);
+            }
+      }
+      __syncthreads();
+      double2* Pj = g.P + (size_t)jw * g.N * g.N;
+#pragma unroll 4
+      for (int e = tid; e < 128 * 128; e += GT8) {
+        const int gi = ti * TM + (e >> 7), gj = tj * TN + c * 128 + (e & 127);
+        if (gi < g.N && gj <= gi) {
+          const float2 x = E[e];
+          double2* p = Pj + (size_t)gi * g.N + gj;
+          double2 y = *p;
+          y.x -= (double)x.x;
+          y.y -= (double)x.y;
+          *p = y;
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * 64 + cb * 32 + l32;
+        const float re = cr[rb][cb][v], im = ci[rb][cb][v];
+        if constexpr (OUT == OUT_TILED) {
+          const int t = tj * TN + col;
+          const size_t bs = (size_t)ti * g.nst_out + t / TK;
+          const int kk = t % TK;
+          g.M[(bs * 4 + (kk >> 2)) * TR * 4 + row * 4 + (kk & 3)] = make_float2(re, im);
+        } else {
+          const int gi = ti * TM + row, gt = tj * TN + col;
+          if (gi < g.N && gt < g.T) g.M[(size_t)gi * g.ldm + gt] = make_float2(re, im);
+        }
+      }
+}
+
 template <int OUT, int DMA>
 int enable_gemm_lds() {
   static int done = 0;
@@ -628,7 +797,22 @@ int launch_gemm_as(hipStream_t s, const GemmArgs& a, int grid, const char* name)
 }
 
 template <int OUT>
+int launch_gemm8(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
+  static int attr = 0;
+  if (!attr) {
+    GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm8_bf16x3_kernel<OUT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds));
+    attr = 1;
+  }
+  ProfScope prof(s, name);
+  hipLaunchKernelGGL((gemm8_bf16x3_kernel<OUT>), dim3(grid), dim3(GT8), kGemmLds, s, a);
+  GW_LAUNCHED("gemm8_bf16x3_kernel");
+  return GW_OK;
+}
+
+template <int OUT>
 int launch_gemm(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
+  if (g_gemm_staging == 3) return launch_gemm8<OUT>(s, a, grid, name);
   return g_gemm_staging == 2 ? launch_gemm_as<OUT, 1>(s, a, grid, name) : launch_gemm_as<OUT, 0>(s, a, grid, name);
 }
 
