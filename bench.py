@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import math
 import os
 import sys
@@ -143,8 +144,9 @@ def summarize_pmc(a) -> int:
         fb = fetch.get(k, 0.0) * 1024.0 * (kf or 1.0)
         wb = write.get(k, 0.0) * 1024.0 * (kw or 1.0)
         out["kernels"][k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
-    # the projection runs as the OUT_TILED instance of the split-BF16 GEMM core
-    dom = next((k for k in out["kernels"] if k.startswith("gemm_bf16x3_kernel<0,")), None)
+    # the projection runs as the OUT_TILED instance (first template argument 0)
+    # of the split-BF16 GEMM core, 4-wave (gemm_) or 8-wave (gemm8_)
+    dom = next((k for k in out["kernels"] if re.match(r"gemm8?_bf16x3_kernel<0[,>]", k)), None)
     if dom:
         out["kernel"] = "project_bf16_kernel"
         out["symbol"] = dom

@@ -245,9 +245,9 @@ int gw_surrogate_judge(void* stream, const gw_surr_desc* d_host, const float* Y,
  *                         tiles; 2 (default): 256 x 128 output tiles with the
  *                         staging of the next K stage interleaved with the
  *                         MFMAs.
- *   "gemm_staging"        pipeline 2 only: 1 (default): 4 waves, operand
- *                         stages pass through registers into LDS; 2: 4 waves,
- *                         direct global-to-LDS copies; 3: 8 waves (two per
+ *   "gemm_staging"        pipeline 2 only: 1: 4 waves, operand stages pass
+ *                         through registers into LDS; 2: 4 waves, direct
+ *                         global-to-LDS copies; 3 (default): 8 waves (two per
  *                         SIMD), register staging.
  * Values out of range and unknown keys give GW_ERR_INVALID_ARG.  Not
  * thread-safe: set before launching work. */

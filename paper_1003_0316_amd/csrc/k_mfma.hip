@@ -989,7 +989,7 @@ int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32
 // with the c64 M chunk under 256 MB (it is re-read by the accumulation), chosen
 // so that the projection's workgroups fill whole rounds of the 256 CUs.
 int g_bf16_pipeline = 2;
-int g_gemm_staging = 1;
+int g_gemm_staging = 3;
 
 int mfma_default_chunk_pairs(int N, int R, int n_omega, int precision) {
   if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_default_chunk_pairs(N, R, n_omega);

@@ -96,43 +96,72 @@ __global__ void tile_u_kernel(int N, int R, int nI, int nst, const float2* __res
 
 // Pair products F_t = conj(psi_occ) psi_unocc of one chunk -> B-side words
 // [nT][nst][2][WD] (hi, lo); pairs t >= T and k >= R are zero.  Chunk pair t
-// is grid index g = tb + t: occupied row g / nu of po, unoccupied row g % nu of pu.
-__global__ void pair_product_kernel(int R, int nst, int nT, const float2* __restrict__ po,
-                                    const float2* __restrict__ pu, int nu, long tb, int T,
-                                    uint32_t* __restrict__ out) {
-  const size_t total = (size_t)nT * nst * 4 * TR;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int col = (int)(e % TR);
-    const int sh = (int)((e / TR) % 4);
-    const size_t bs = e / (4 * TR);
-    const int st = (int)(bs % nst), blk = (int)(bs / nst);
-    const int t = blk * TR + col;
-    const int r0 = st * TK + sh * 4;
-    uint32_t hw[4], lw[4];
-    const float2* a = nullptr;
-    const float2* b = nullptr;
+// is grid index g = tb + t: occupied row g / nu of po, unoccupied row g % nu of
+// pu.  One workgroup covers 128 pairs x 2 stages (32 complex k): it reads both
+// rows of every pair as 256-byte segments (16 lanes per row), keeps the
+// product in a padded LDS tile, and writes the split words pair-major (64
+// lanes = 64 consecutive pairs = 1 KB per store).
+constexpr int PP_K = 2 * TK;           // complex k per workgroup
+constexpr int PP_PITCH = PP_K + 1;     // complex per LDS row: an odd pitch keeps 32 pair rows on distinct banks
+
+__global__ __launch_bounds__(256) void pair_product_kernel(int R, int nst, int nT, const float2* __restrict__ po,
+                                                           const float2* __restrict__ pu, int nu, long tb, int T,
+                                                           uint32_t* __restrict__ out) {
+  __shared__ float2 F[TR * PP_PITCH];
+  const int blk = blockIdx.y;                 // 128-pair block
+  const int st0 = blockIdx.x * 2;             // first of two stages
+  const int tid = threadIdx.x;
+  const int r0 = st0 * TK;
+  // phase 1: 16 lanes per pair row, 2 complex (one float4) per lane per pass
+  const int sub = tid & 15, prow = tid >> 4;  // 16 pair rows per pass
+#pragma unroll
+  for (int pass = 0; pass < TR / 16; ++pass) {
+    const int p = pass * 16 + prow;
+    const int t = blk * TR + p;
+    const int r = r0 + 2 * sub;
+    float2 f0 = make_float2(0.f, 0.f), f1 = make_float2(0.f, 0.f);
     if (t < T) {
       const long g = tb + t;
-      a = po + (size_t)(g / nu) * R;
-      b = pu + (size_t)(g % nu) * R;
+      const float2* a = po + (size_t)(g / nu) * R;
+      const float2* b = pu + (size_t)(g % nu) * R;
+      float2 x0 = make_float2(0.f, 0.f), x1 = x0, y0 = x0, y1 = x0;
+      if (r + 1 < R && ((R & 1) == 0)) {
+        const float4 xa = *reinterpret_cast<const float4*>(a + r);
+        const float4 yb = *reinterpret_cast<const float4*>(b + r);
+        x0 = make_float2(xa.x, xa.y); x1 = make_float2(xa.z, xa.w);
+        y0 = make_float2(yb.x, yb.y); y1 = make_float2(yb.z, yb.w);
+      } else {
+        if (r < R) { x0 = a[r]; y0 = b[r]; }
+        if (r + 1 < R) { x1 = a[r + 1]; y1 = b[r + 1]; }
+      }
+      f0 = make_float2(x0.x * y0.x + x0.y * y0.y, x0.x * y0.y - x0.y * y0.x);
+      f1 = make_float2(x1.x * y1.x + x1.y * y1.y, x1.x * y1.y - x1.y * y1.x);
     }
+    F[p * PP_PITCH + 2 * sub] = f0;
+    F[p * PP_PITCH + 2 * sub + 1] = f1;
+  }
+  __syncthreads();
+  // phase 2: lane = pair, 4 complex k per item; 128 pairs x 8 groups per workgroup
+#pragma unroll
+  for (int it = 0; it < (TR * PP_K / 4) / 256; ++it) {
+    const int item = it * 256 + tid;
+    const int p = item & (TR - 1), grp = item >> 7;       // grp: 0..7 (stage = grp / 4, sh = grp % 4)
+    uint32_t hw[4], lw[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float fr = 0.f, fi = 0.f;
-      if (a && r0 + j < R) {
-        const float2 x = a[r0 + j], y = b[r0 + j];
-        fr = x.x * y.x + x.y * y.y;
-        fi = x.x * y.y - x.y * y.x;
-      }
+      const float2 f = F[p * PP_PITCH + grp * 4 + j];
       float rh, rl, ih, il;
-      split2(fr, rh, rl);
-      split2(fi, ih, il);
+      split2(f.x, rh, rl);
+      split2(f.y, ih, il);
       hw[j] = pack_bf16(rh, ih);
       lw[j] = pack_bf16(rl, il);
     }
-    uint32_t* o = out + bs * 2 * WD + lane_off(sh, col);
-    *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-    *reinterpret_cast<uint4*>(o + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    const int st = st0 + (grp >> 2);
+    if (st < nst) {
+      uint32_t* o = out + ((size_t)blk * nst + st) * 2 * WD + lane_off(grp & 3, p);
+      *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      *reinterpret_cast<uint4*>(o + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
   }
 }
 
@@ -780,8 +809,8 @@ int launch_tile_u(hipStream_t s, const TiledDims& d, int N, int R, const float2*
 int launch_pair_product(hipStream_t s, const TiledDims& d, int R, const float2* po, const float2* pu, int nu, long tb,
                         int T, uint32_t* Q) {
   ProfScope prof(s, "pair_product_kernel");
-  hipLaunchKernelGGL(pair_product_kernel, dim3(stream_blocks((size_t)d.nT * d.nstR * 4 * TR)), dim3(256), 0, s, R,
-                     d.nstR, d.nT, po, pu, nu, tb, T, Q);
+  hipLaunchKernelGGL(pair_product_kernel, dim3((d.nstR + 1) / 2, d.nT), dim3(256), 0, s, R, d.nstR, d.nT, po, pu, nu,
+                     tb, T, Q);
   GW_LAUNCHED("pair_product_kernel");
   return GW_OK;
 }

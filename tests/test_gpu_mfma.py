@@ -153,7 +153,7 @@ def test_split_bf16_kernel_variants(lib, pipeline, pv, staging):
     finally:
         lib.gw_set_tuning("bf16_pipeline", 2)
         lib.gw_set_tuning("projection_variant", 2)
-        lib.gw_set_tuning("gemm_staging", 1)
+        lib.gw_set_tuning("gemm_staging", 3)
     Ur, pr = _rounded(inp)
     ref = orc.polarization(Ur, pr, inp.eps, inp.omega, 3, kq=inp.kq)
     err = orc.rel_fro(P.cpu().numpy(), ref)
