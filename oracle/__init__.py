@@ -5,4 +5,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 library and its Python binding) never imports it, and it never imports the
 product path.  Inputs come from ``gwsynth`` (random draws only).
 """
-from . import polarization, mlp, surrogate, precision  # noqa: F401
+from . import polarization, mlp, surrogate, precision, selfenergy  # noqa: F401
