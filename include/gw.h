@@ -230,6 +230,57 @@ int gw_surrogate_judge(void* stream, const gw_surr_desc* d_host, const float* Y,
                        int n_sample, const int* sample_k_host, const int* sample_occ_host, double* err, void* ws,
                        size_t ws_bytes);
 
+/* ------------------------------------------------- correlation self-energy
+ * Diagonal correlation self-energy on the imaginary axis, Eq. SEc_AC (the
+ * analytic continuation of Eq. SEc_MB), for a list of states (set s, band n):
+ *
+ *   sigma[i][o] = -(1/2pi) sum_t sum_n' sum_{mu,nu} conj(m_mu) Wc_{mu nu}(t) m_nu  (integrated)
+ *               = -(1/2pi) sum_t sum_n'  int dw' q_{t n'}(i w') / (i w_o + i w' - (e_n' - mu))
+ *
+ * with m_I = sum_r U_Ir conj(psi_{s,n}(r)) psi_{s',n'}(r) (Eq. proj_MB), s' =
+ * (s + t) mod n_k, n' over all n_bands bands of set s', Wc(t) = W(t) - diag(v),
+ * and q_{t n'}(i w') = m^H Wc(t, i w') m between the mesh points interpolated
+ * by a cubic spline in lambda = w/(1+w) (text after Eq. SEc_AC; zero slope at
+ * w = 0, at the last point the slope of the w^-2 tail q_L (w_L/w)^2 used
+ * beyond it), integrated in closed form.  W is even in w (P depends on w^2),
+ * so the integral over w' < 0 is folded onto w' > 0.  No Gamma-point terms.
+ *
+ *   precision       GW_FP64 (U, psi c128) or GW_SPLIT_BF16 (U, psi c64; the
+ *                   quadratic forms on the split-BF16 matrix cores)
+ *   mesh_host       n_mesh (2..64) imaginary frequencies of W, mesh[0] = 0,
+ *                   strictly increasing
+ *   omega_out_host  n_out (1..64) frequencies >= 0 at which sigma is returned
+ *   state_*_host    n_states states (set in [0,n_k), band in [0,n_bands))
+ *   mu              chemical potential; every e - mu must be nonzero
+ *   U, psi, eps     as for gw_polarization (eps device and eps_host host)
+ *   W_host          host array of n_k device pointers: W(t) [n_mesh][N][N]
+ *                   c128 for transfer t, e.g. gw_screen of the polarization
+ *                   whose kq_host is (k + t) mod n_k
+ *   v               device [N] FP64 Coulomb diagonal
+ *   sigma           device [n_states][n_out] c128, overwritten
+ * Workspace from gw_sigma_c_workspace_size; errors as for gw_polarization. */
+typedef struct {
+  int precision, n_k, N, R, n_bands;
+  int n_mesh;
+  const double* mesh_host;
+  int n_out;
+  const double* omega_out_host;
+  int n_states;
+  const int* state_set_host;
+  const int* state_band_host;
+  double mu;
+  const void* U;
+  const void* psi;
+  const double* eps;
+  const double* eps_host;
+  const void* const* W_host;
+  const double* v;
+  void* sigma;
+} gw_sigma_desc;
+
+int gw_sigma_c_workspace_size(const gw_sigma_desc* d_host, size_t* bytes);
+int gw_sigma_c(void* stream, const gw_sigma_desc* d_host, void* ws, size_t ws_bytes);
+
 /* --------------------------------------------------------------------- tuning
  * Process-wide kernel-variant switches for the split-BF16 path (all results
  * stay within the same tolerances; the work done is identical).  Keys:

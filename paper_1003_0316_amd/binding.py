@@ -53,6 +53,22 @@ class GwPolDesc(ctypes.Structure):
     ]
 
 
+class GwSigmaDesc(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int), ("n_k", ctypes.c_int), ("N", ctypes.c_int), ("R", ctypes.c_int),
+        ("n_bands", ctypes.c_int),
+        ("n_mesh", ctypes.c_int), ("mesh_host", ctypes.POINTER(ctypes.c_double)),
+        ("n_out", ctypes.c_int), ("omega_out_host", ctypes.POINTER(ctypes.c_double)),
+        ("n_states", ctypes.c_int),
+        ("state_set_host", ctypes.POINTER(ctypes.c_int)), ("state_band_host", ctypes.POINTER(ctypes.c_int)),
+        ("mu", ctypes.c_double),
+        ("U", ctypes.c_void_p), ("psi", ctypes.c_void_p),
+        ("eps", ctypes.c_void_p), ("eps_host", ctypes.POINTER(ctypes.c_double)),
+        ("W_host", ctypes.POINTER(ctypes.c_void_p)), ("v", ctypes.c_void_p),
+        ("sigma", ctypes.c_void_p),
+    ]
+
+
 _sz = ctypes.c_size_t
 _vp = ctypes.c_void_p
 _ci = ctypes.c_int
@@ -100,12 +116,16 @@ _lib.gw_profile_enable.argtypes = [_ci]
 _lib.gw_profile_reset.argtypes = []
 _lib.gw_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(_ci), ctypes.POINTER(ctypes.c_double)]
 
+_lib.gw_sigma_c_workspace_size.argtypes = [ctypes.POINTER(GwSigmaDesc), ctypes.POINTER(_sz)]
+_lib.gw_sigma_c.argtypes = [_vp, ctypes.POINTER(GwSigmaDesc), _vp, _sz]
+
 EXPORTED = ("gw_last_error", "gw_version", "gw_project_workspace_size", "gw_project",
             "gw_polarization_workspace_size", "gw_polarization", "gw_screen_workspace_size", "gw_screen",
             "gw_profile_enable", "gw_profile_reset", "gw_profile_query",
             "gw_mlp_sizes", "gw_mlp_sync_bf16", "gw_mlp_forward", "gw_mlp_loss", "gw_mlp_workspace_size",
             "gw_mlp_backward", "gw_mlp_adam_step", "gw_surrogate_workspace_size", "gw_surrogate_features",
-            "gw_surrogate_targets", "gw_surrogate_apply", "gw_surrogate_judge", "gw_set_tuning")
+            "gw_surrogate_targets", "gw_surrogate_apply", "gw_surrogate_judge", "gw_set_tuning",
+            "gw_sigma_c_workspace_size", "gw_sigma_c")
 
 
 def lib():
@@ -470,3 +490,78 @@ def gw_surrogate_judge(args: SurrogateArgs, Y, ldy, P_sample, sample_rows, strea
 
 def gw_set_tuning(key: str, value: int) -> None:
     _check(_lib.gw_set_tuning(key.encode(), int(value)))
+
+
+class SigmaCall:
+    """Marshalled arguments of one gw_sigma_c call (keeps host arrays alive)."""
+
+    def __init__(self, U, psi, eps_host, W_by_transfer, v, mesh, omega_out, states, mu, *, precision="fp64",
+                 eps_dev=None, sigma=None):
+        prec = _prec(precision)
+        dt = _cdtype(prec)
+        _dev_tensor(U, "U", dt)
+        _dev_tensor(psi, "psi", dt)
+        N, R = U.shape
+        n_k, nb = psi.shape[0], psi.shape[1]
+        self.eps_host = np.ascontiguousarray(eps_host, dtype=np.float64)
+        if self.eps_host.shape != (n_k, nb):
+            raise ValueError(f"eps must be [{n_k}][{nb}]")
+        self.eps_dev = eps_dev if eps_dev is not None else torch.from_numpy(self.eps_host).to(U.device)
+        _dev_tensor(self.eps_dev, "eps_dev", torch.float64)
+        if len(W_by_transfer) != n_k:
+            raise ValueError("one W per momentum transfer (n_k of them) is required")
+        self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
+        for W in W_by_transfer:
+            _dev_tensor(W, "W", torch.complex128)
+            if tuple(W.shape) != (self.mesh.shape[0], N, N):
+                raise ValueError("W has the wrong shape")
+        _dev_tensor(v, "v", torch.float64)
+        self.omega_out = np.ascontiguousarray(omega_out, dtype=np.float64)
+        st = np.asarray(states, dtype=np.int32).reshape(-1, 2)
+        self.state_set = np.ascontiguousarray(st[:, 0])
+        self.state_band = np.ascontiguousarray(st[:, 1])
+        if sigma is None:
+            sigma = torch.empty((st.shape[0], self.omega_out.shape[0]), dtype=torch.complex128, device=U.device)
+        _dev_tensor(sigma, "sigma", torch.complex128)
+        self.sigma = sigma
+        self.W_ptrs = (ctypes.c_void_p * n_k)(*[W.data_ptr() for W in W_by_transfer])
+        self.tensors = (U, psi, v, tuple(W_by_transfer))
+        d = GwSigmaDesc()
+        d.precision, d.n_k, d.N, d.R, d.n_bands = prec, n_k, N, R, nb
+        d.n_mesh = int(self.mesh.shape[0])
+        d.mesh_host = self.mesh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.n_out = int(self.omega_out.shape[0])
+        d.omega_out_host = self.omega_out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.n_states = int(st.shape[0])
+        d.state_set_host = self.state_set.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        d.state_band_host = self.state_band.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        d.mu = float(mu)
+        d.U, d.psi = U.data_ptr(), psi.data_ptr()
+        d.eps = self.eps_dev.data_ptr()
+        d.eps_host = self.eps_host.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.W_host = ctypes.cast(self.W_ptrs, ctypes.POINTER(ctypes.c_void_p))
+        d.v = v.data_ptr()
+        d.sigma = sigma.data_ptr()
+        self.desc = d
+
+    def workspace_size(self) -> int:
+        out = _sz(0)
+        _check(_lib.gw_sigma_c_workspace_size(ctypes.byref(self.desc), ctypes.byref(out)))
+        return out.value
+
+    def run(self, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        nbytes = self.workspace_size()
+        if ws is None:
+            ws = workspace(nbytes, self.sigma.device, "sigma")
+        _check(_lib.gw_sigma_c(_stream(stream), ctypes.byref(self.desc), ws.data_ptr(), ws.numel()))
+        return self.sigma
+
+
+def gw_sigma_c(U, psi, eps_host, W_by_transfer, v, mesh, omega_out, states, mu, **kw) -> torch.Tensor:
+    """Diagonal correlation self-energy sigma[state][o] on the imaginary axis
+    (Eq. SEc_AC, see gw.h): complex128 [n_states][n_out], enqueued on the
+    current stream.  W_by_transfer[t] is W(t) [n_mesh][N][N] (not W - v)."""
+    ws = kw.pop("ws", None)
+    stream = kw.pop("stream", None)
+    return SigmaCall(U, psi, eps_host, W_by_transfer, v, mesh, omega_out, states, mu, **kw).run(ws, stream)
+

@@ -26,4 +26,10 @@ int tiled_project(hipStream_t s, int N, int R, int n_occ, int n_unocc, const flo
 int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
                        const OmegaList& om, void* ws);
 
+// Correlation self-energy, split-BF16 quadratic forms (k_tiled.hip).
+size_t tiled_sigma_workspace(int N, int R, int nb);
+int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const float2* U, bool tile_u,
+                          const float2* psi_state, const float2* psi_all, const double2* W, const double* v,
+                          double* q, void* ws);
+
 }  // namespace gw

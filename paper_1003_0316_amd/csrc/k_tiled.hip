@@ -232,6 +232,84 @@ __global__ void scale_split_kernel(int nI, int nIe, int nstT, int Tp, int n_omeg
   }
 }
 
+// W^c_j = W_j - diag(v) (c128 [N][N]) -> A-side words [nI][nstN][4][WD]
+// (conj hi, lo, swap hi, lo), zero outside N x N.
+__global__ void tile_wc_kernel(int N, int nI, int nst, const double2* __restrict__ W, const double* __restrict__ v,
+                               uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nI * nst * 4 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % TR);
+    const int sh = (int)((e / TR) % 4);
+    const size_t bs = e / (4 * TR);
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int I = blk * TR + row;
+    const int c0 = st * TK + sh * 4;
+    uint32_t w[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double2 x = make_double2(0.0, 0.0);
+      const int c = c0 + j;
+      if (I < N && c < N) {
+        x = W[(size_t)I * N + c];
+        if (c == I) x.x -= v[I];
+      }
+      float rh, rl, ih, il;
+      split2((float)x.x, rh, rl);
+      split2((float)x.y, ih, il);
+      w[0][j] = pack_bf16(rh, -ih);
+      w[1][j] = pack_bf16(rl, -il);
+      w[2][j] = pack_bf16(ih, rh);
+      w[3][j] = pack_bf16(il, rl);
+    }
+    uint32_t* o = out + bs * 4 * WD + lane_off(sh, row);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<uint4*>(o + (size_t)q * WD) = make_uint4(w[q][0], w[q][1], w[q][2], w[q][3]);
+  }
+}
+
+// Columns of M (c64 rows [N][ldm], columns < nb valid) -> B-side words
+// [nb_pad/128][nstN][2][WD] with the reduction index running over the rows of
+// M (hi, lo); zero for columns >= nb and rows >= N.
+__global__ void tile_cols_kernel(int N, int nb, int nTb, int nst, const float2* __restrict__ M, long ldm,
+                                 uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nTb * nst * 4 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(e % TR);
+    const int sh = (int)((e / TR) % 4);
+    const size_t bs = e / (4 * TR);
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int c = blk * TR + col;
+    const int r0 = st * TK + sh * 4;
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float2 x = make_float2(0.f, 0.f);
+      if (c < nb && r0 + j < N) x = M[(size_t)(r0 + j) * ldm + c];
+      float rh, rl, ih, il;
+      split2(x.x, rh, rl);
+      split2(x.y, ih, il);
+      hw[j] = pack_bf16(rh, ih);
+      lw[j] = pack_bf16(rl, il);
+    }
+    uint32_t* o = out + bs * 2 * WD + lane_off(sh, col);
+    *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    *reinterpret_cast<uint4*>(o + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+  }
+}
+
+// q[n'] = Re sum_mu conj(M[mu][n']) Y[mu][n'] (FP64 accumulation).
+__global__ void coldot_f32_kernel(int N, int nb, const float2* __restrict__ M, const float2* __restrict__ Y, long ld,
+                                  double* __restrict__ q) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nb) return;
+  double acc = 0.0;
+  for (int r = 0; r < N; ++r) {
+    const float2 m = M[(size_t)r * ld + c], y = Y[(size_t)r * ld + c];
+    acc += (double)m.x * (double)y.x + (double)m.y * (double)y.y;
+  }
+  q[c] = acc;
+}
+
 // --------------------------------------------------------------- GEMM core
 
 // Workgroups are handed to the 8 XCDs round-robin by linear id; renumber them
@@ -956,6 +1034,91 @@ int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Ch
     b.N = d.N;
     b.P = reinterpret_cast<double2*>(d.P);
     if ((st = launch_gemm<OUT_HERK>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")) != GW_OK) return st;
+  }
+  return GW_OK;
+}
+
+// ------------------------------------------------ correlation self-energy
+// Quadratic forms q_j[n'] = m^H (W_j - diag v) m of Eq. SEc_AC for one state
+// and one transfer, split BF16 on the GEMM core: the projections m of the
+// products conj(psi_state) psi_n' (all bands n'), then Y_j = W^c_j M and the
+// column dots.
+struct SigmaDims {
+  int nI, nstR, nstN, nbp, nTb;
+  size_t u_words, q_words, m_c64, mt_words, w_words;
+  SigmaDims(int N, int R, int nb) {
+    nI = cdiv(N, TR);
+    nstR = cdiv(R, TK);
+    nstN = cdiv(N, TK);
+    nbp = cdiv(nb, TN) * TN;
+    nTb = nbp / TR;
+    u_words = (size_t)nI * nstR * 4 * WD;
+    q_words = (size_t)nTb * nstR * 2 * WD;
+    m_c64 = (size_t)N * nbp;
+    mt_words = (size_t)nTb * nstN * 2 * WD;
+    w_words = (size_t)nI * nstN * 4 * WD;
+  }
+  size_t bytes() const {
+    return align_up(u_words * 4) + align_up(q_words * 4) + 2 * align_up(m_c64 * 8) + align_up(mt_words * 4) +
+           align_up(w_words * 4);
+  }
+};
+
+size_t tiled_sigma_workspace(int N, int R, int nb) { return SigmaDims(N, R, nb).bytes(); }
+
+int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const float2* U, bool tile_u,
+                          const float2* psi_state, const float2* psi_all, const double2* W, const double* v,
+                          double* q, void* ws) {
+  SigmaDims d(N, R, nb);
+  Carver cv(ws);
+  uint32_t* Uw = cv.take<uint32_t>(d.u_words);
+  uint32_t* Q = cv.take<uint32_t>(d.q_words);
+  float2* M = cv.take<float2>(d.m_c64);
+  float2* Y = cv.take<float2>(d.m_c64);
+  uint32_t* Mt = cv.take<uint32_t>(d.mt_words);
+  uint32_t* Ww = cv.take<uint32_t>(d.w_words);
+  int st;
+  TiledDims td(N, R, nb, 0);
+  if (tile_u && (st = launch_tile_u(s, td, N, R, U, Uw)) != GW_OK) return st;
+  if ((st = launch_pair_product(s, td, R, psi_state, psi_all, nb, 0, nb, Q)) != GW_OK) return st;
+  GemmArgs a{};
+  a.A = Uw;
+  a.B = Q;
+  a.b_words = 2;
+  a.nst = d.nstR;
+  a.a_bstride = (size_t)d.nstR * 4 * WD;
+  a.b_bstride = (size_t)d.nstR * 2 * WD;
+  a.nI = d.nI;
+  a.nTj = d.nbp / TN;
+  a.N = N;
+  a.T = nb;
+  a.M = M;
+  a.ldm = d.nbp;
+  if ((st = launch_gemm<OUT_ROWS>(s, a, d.nI * a.nTj, "sigma_project_kernel")) != GW_OK) return st;
+  hipLaunchKernelGGL(tile_cols_kernel, dim3(stream_blocks((size_t)d.nTb * d.nstN * 4 * TR)), dim3(256), 0, s, N, nb,
+                     d.nTb, d.nstN, M, (long)d.nbp, Mt);
+  GW_LAUNCHED("tile_cols_kernel");
+  for (int j = 0; j < n_mesh; ++j) {
+    hipLaunchKernelGGL(tile_wc_kernel, dim3(stream_blocks((size_t)d.nI * d.nstN * 4 * TR)), dim3(256), 0, s, N, d.nI,
+                       d.nstN, W + (size_t)j * N * N, v, Ww);
+    GW_LAUNCHED("tile_wc_kernel");
+    GemmArgs b{};
+    b.A = Ww;
+    b.B = Mt;
+    b.b_words = 2;
+    b.nst = d.nstN;
+    b.a_bstride = (size_t)d.nstN * 4 * WD;
+    b.b_bstride = (size_t)d.nstN * 2 * WD;
+    b.nI = d.nI;
+    b.nTj = d.nbp / TN;
+    b.N = N;
+    b.T = nb;
+    b.M = Y;
+    b.ldm = d.nbp;
+    if ((st = launch_gemm<OUT_ROWS>(s, b, d.nI * b.nTj, "sigma_wm_kernel")) != GW_OK) return st;
+    hipLaunchKernelGGL(coldot_f32_kernel, dim3(cdiv(nb, 256)), dim3(256), 0, s, N, nb, M, Y, (long)d.nbp,
+                       q + (size_t)j * nb);
+    GW_LAUNCHED("coldot_f32_kernel");
   }
   return GW_OK;
 }

@@ -159,3 +159,56 @@ def test_tuning_switches_validate(b):
         assert L.gw_set_tuning(key.encode(), default) == 0
     assert L.gw_set_tuning(b"no_such_key", 1) == -1
     assert L.gw_set_tuning(None, 1) == -1
+
+
+def _sigma_desc(b, **over):
+    keep = {}
+    d = b.GwSigmaDesc()
+    d.precision, d.n_k, d.N, d.R, d.n_bands = 0, 2, 8, 16, 5
+    keep["mesh"] = np.asarray(over.pop("mesh", (0.0, 0.5, 2.0)), dtype=np.float64)
+    d.n_mesh = keep["mesh"].size
+    d.mesh_host = keep["mesh"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    keep["out"] = np.asarray(over.pop("out", (0.0, 1.0)), dtype=np.float64)
+    d.n_out = keep["out"].size
+    d.omega_out_host = keep["out"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    keep["ss"] = np.asarray(over.pop("sets", (0,)), dtype=np.int32)
+    keep["sb"] = np.asarray(over.pop("bands", (1,)), dtype=np.int32)
+    d.n_states = keep["ss"].size
+    d.state_set_host = keep["ss"].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    d.state_band_host = keep["sb"].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    keep["eps"] = np.tile(np.array([-0.5, -0.2, 0.1, 0.4, 0.9]), (2, 1))
+    d.eps_host = keep["eps"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.mu = over.pop("mu", 0.0)
+    fake = 0x7F0000001000   # never dereferenced: every call below fails validation first
+    d.U = d.psi = d.eps = d.v = d.sigma = fake
+    keep["W"] = (ctypes.c_void_p * 2)(fake, fake)
+    d.W_host = ctypes.cast(keep["W"], ctypes.POINTER(ctypes.c_void_p))
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d, keep
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(mesh=(0.1, 0.5, 2.0)), -1),            # the mesh must start at 0
+    (dict(mesh=(0.0, 0.5, 0.5)), -1),            # strictly increasing
+    (dict(mesh=tuple(np.linspace(0, 1, 65))), -1),
+    (dict(out=(-1.0,)), -1),
+    (dict(mu=0.1), -1),                          # a band energy at the chemical potential
+    (dict(bands=(5,)), -1),
+    (dict(sets=(2,)), -1),
+    (dict(precision=1), -2),                     # FP32 quadratic forms are not offered
+])
+def test_sigma_validation(b, kw, status):
+    d, keep = _sigma_desc(b, **kw)
+    out = ctypes.c_size_t(0)
+    assert b.lib().gw_sigma_c_workspace_size(ctypes.byref(d), ctypes.byref(out)) == status
+    assert b.lib().gw_sigma_c(None, ctypes.byref(d), None, 0) == status
+
+
+def test_sigma_workspace_and_null_w(b):
+    d, keep = _sigma_desc(b)
+    out = ctypes.c_size_t(0)
+    assert b.lib().gw_sigma_c_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 0 and out.value > 0
+    assert b.lib().gw_sigma_c(None, ctypes.byref(d), None, 0) == -3       # no workspace
+    keep["W"][1] = None
+    assert b.lib().gw_sigma_c_workspace_size(ctypes.byref(d), ctypes.byref(out)) == -1
