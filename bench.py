@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--traffic-driver", action="store_true",
                     help="only run the main explicit-band polarization of one k-point on Gaussian inputs of the "
                          "workload's shape (no device QR; the launch sequence for HBM traffic counters)")
+    ap.add_argument("--sigma", action="store_true",
+                    help="measure the correlation self-energy instead (supercell workload: W for every momentum "
+                         "transfer, then Sigma_c(i w) of the highest occupied and lowest unoccupied state)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c5.json"),
                     help="measured per-launch HBM traffic of the dominant kernel (from rocprofv3 --pmc)")
     return ap.parse_args()
@@ -108,6 +111,85 @@ def traffic_driver(a) -> int:
     call.run()
     torch.cuda.synchronize()
     print(json.dumps({"traffic_driver": a.workload, "pairs": shp.n_occ * cutoff, "precision": a.precision}))
+    return 0
+
+
+def sigma_bench(a) -> int:
+    """Correlation self-energy (Eq. SEc_AC) on the supercell-shaped workload
+    (N_k=8, N=3000, R=32768, 128 + 2000 bands, 16 imaginary frequencies):
+    W(t) for all 8 momentum transfers (split-BF16 polarization, FP64
+    screening), then Sigma_c(i w) at the 16 mesh frequencies for the highest
+    occupied and the lowest unoccupied band of set 0, split BF16.  Prints one
+    JSON line; the timed region is the self-energy call."""
+    import numpy as np
+    import torch
+
+    import gwsynth
+    from paper_1003_0316_amd import binding as gw
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shp = gwsynth.SHAPES["c3"]
+    inp = gwsynth.generate_torch(shp, dev, log=log)
+    v = torch.from_numpy(inp.v).to(dev)
+    mesh = inp.omega
+    n_k = shp.n_k
+    t0 = time.time()
+    Ws = []
+    for t in range(n_k):
+        kq = (np.arange(n_k) + t) % n_k
+        P = gw.gw_polarization(inp.U, inp.psi, inp.eps, mesh, shp.n_occ, precision="split_bf16", kq=kq)
+        W, info = gw.gw_screen(P, v)
+        torch.cuda.synchronize()
+        del P
+        if int(info.abs().sum()) != 0:
+            log(f"WARNING: screening reported non-positive pivots for transfer {t}")
+        Ws.append(W)
+        log(f"W for transfer {t} done")
+    t_w = time.time() - t0
+    mu = 0.5 * (inp.eps[:, :shp.n_occ].max() + inp.eps[:, shp.n_occ:].min())
+    states = [(0, shp.n_occ - 1), (0, shp.n_occ)]
+    call = gw.SigmaCall(inp.U, inp.psi, inp.eps, Ws, v, mesh, mesh, states, mu, precision="split_bf16")
+    for _ in range(a.warmup):
+        call.run()
+    torch.cuda.synchronize()
+    gw.gw_profile_reset()
+    gw.gw_profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        sig = call.run()
+    e1.record()
+    torch.cuda.synchronize()
+    gw.gw_profile_enable(False)
+    ms = e0.elapsed_time(e1) / a.steps
+    s_np = sig.cpu().numpy()
+    n_wm, t_wm = gw.gw_profile_query("sigma_wm_kernel")
+    n_pr, t_pr = gw.gw_profile_query("sigma_project_kernel")
+    nb = shp.n_bands
+    n_st = len(states)
+    flops_wm = 8.0 * shp.N * shp.N * nb * len(mesh) * n_k * n_st * a.steps
+    flops_pr = 8.0 * shp.N * shp.R * nb * n_k * n_st * a.steps
+    achieved = flops_wm / (t_wm * 1e-3) / 1e12
+    props = {"sigma_at_0_is_real": bool(np.all(np.abs(s_np[:, 0].imag) <= 1e-9 * np.abs(s_np[:, 0]))),
+             "im_negative_for_w_gt_0": bool(np.all(s_np[:, 1:].imag < 0))}
+    out = {"metric": "Sigma_c(i w) s/state (Eq. SEc_AC, all 8 momentum transfers, all 2128 bands, 16 frequencies)",
+           "value": round(ms / 1e3 / n_st, 4), "unit": "s/state", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": round(ms, 2), "higher_is_better": False, "dtype": "bf16x3 (split hi/lo), fp32 acc, fp64 weights",
+           "data": "synthetic (seeded; paper-shaped)",
+           "config": {"workload": "c3: N_k=8, N=3000, R=32768, 128 occ + 2000 unocc bands, 16 imaginary frequencies",
+                      "states": states, "mu": mu},
+           "w_all_transfers_s": round(t_w, 2),
+           "kernels_ms_per_step": {"sigma_wm_kernel": round(t_wm / a.steps, 2),
+                                   "sigma_project_kernel": round(t_pr / a.steps, 2)},
+           "roofline": {"bound": "mfma", "kernel": "sigma_wm_kernel", "achieved": round(achieved, 2),
+                        "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_TFLOPS["bf16"], 4), "traffic": None,
+                        "avg_launch_ms": round(t_wm / max(1, n_wm), 4),
+                        "alg_flops_per_launch": flops_wm / max(1, n_wm), "launches": n_wm},
+           "projection_tflops": round(flops_pr / (t_pr * 1e-3) / 1e12, 2) if t_pr > 0 else None,
+           "sigma": [[[float(x.real), float(x.imag)] for x in row] for row in s_np],
+           "properties": props}
+    print(json.dumps(out))
     return 0
 
 
@@ -175,6 +257,8 @@ def main() -> int:
         return summarize_pmc(a)
     if a.traffic_driver:
         return traffic_driver(a)
+    if a.sigma:
+        return sigma_bench(a)
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build runs on one GPU only "
               f"(the k-point / occupied-band shards and the reduce-scatter of P over frequencies are "

@@ -227,17 +227,39 @@ __global__ __launch_bounds__(256) void zgemm_shift_kernel(int N, int nb, const d
     }
 }
 
-// q[n'] = Re sum_mu conj(M[mu][n']) Y[mu][n'].
-__global__ void coldot_f64_kernel(int N, int nb, const double2* __restrict__ M, const double2* __restrict__ Y,
-                                  double* __restrict__ q) {
+// q[n'] = Re sum_mu conj(M[mu][n']) Y[mu][n'] in two fixed-order passes (32
+// columns x one chunk of rows per workgroup, then the chunks in order).
+constexpr int CD_CHUNKS64 = 16;
+
+__global__ __launch_bounds__(256) void coldot_f64_kernel(int N, int nb, const double2* __restrict__ M,
+                                                         const double2* __restrict__ Y, int rows_per_chunk,
+                                                         double* __restrict__ part) {
+  __shared__ double red[8][32];
+  const int cx = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  const int c = blockIdx.x * 32 + cx;
+  const int r0 = blockIdx.y * rows_per_chunk, r1 = min(N, r0 + rows_per_chunk);
+  double acc = 0.0;
+  if (c < nb)
+    for (int r = r0 + ry; r < r1; r += 8) {
+      const double2 m = M[(size_t)r * nb + c], y = Y[(size_t)r * nb + c];
+      acc = fma(m.x, y.x, fma(m.y, y.y, acc));
+    }
+  red[ry][cx] = acc;
+  __syncthreads();
+  if (ry == 0 && c < nb) {
+    double t = red[0][cx];
+#pragma unroll
+    for (int g = 1; g < 8; ++g) t += red[g][cx];
+    part[(size_t)blockIdx.y * nb + c] = t;
+  }
+}
+
+__global__ void coldot_sum_kernel(int nb, int chunks, const double* __restrict__ part, double* __restrict__ q) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nb) return;
-  double acc = 0.0;
-  for (int r = 0; r < N; ++r) {
-    const double2 m = M[(size_t)r * nb + c], y = Y[(size_t)r * nb + c];
-    acc = fma(m.x, y.x, fma(m.y, y.y, acc));
-  }
-  q[c] = acc;
+  double t = 0.0;
+  for (int k = 0; k < chunks; ++k) t += part[(size_t)k * nb + c];
+  q[c] = t;
 }
 
 // sigma[o] += -(1/2pi) sum_b sum_j w[b][o][j] q[j][b]; one block per output
@@ -324,10 +346,11 @@ SigmaWs sigma_ws(const gw_sigma_desc& d) {
   SigmaWs w;
   const int ni = d.n_mesh - 1;
   size_t t = align_up((size_t)ni * 4 * d.n_mesh * sizeof(double)) +
-             align_up((size_t)d.n_bands * d.n_out * d.n_mesh * sizeof(double2)) +
+             align_up((size_t)d.n_k * d.n_bands * d.n_out * d.n_mesh * sizeof(double2)) +
              align_up((size_t)d.n_mesh * d.n_bands * sizeof(double));
   if (d.precision == GW_FP64) {
-    t += 2 * align_up((size_t)d.N * d.n_bands * sizeof(double2));
+    t += 2 * align_up((size_t)d.N * d.n_bands * sizeof(double2)) +
+         align_up((size_t)CD_CHUNKS64 * d.n_bands * sizeof(double));
   } else {
     w.quad = tiled_sigma_workspace(d.N, d.R, d.n_bands);
     t += align_up(w.quad);
@@ -364,7 +387,7 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
   const int nb = d.n_bands, ni = d.n_mesh - 1;
   Carver cv(ws);
   double* C = cv.take<double>((size_t)ni * 4 * d.n_mesh);
-  double2* wts = cv.take<double2>((size_t)nb * d.n_out * d.n_mesh);
+  double2* wts = cv.take<double2>((size_t)d.n_k * nb * d.n_out * d.n_mesh);   // per band set
   double* q = cv.take<double>((size_t)d.n_mesh * nb);
   double2* sig = static_cast<double2*>(d.sigma);
   hipLaunchKernelGGL(spline_basis_kernel, dim3(1), dim3(kMaxMesh), 0, s, mesh, C);
@@ -373,13 +396,22 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
                      d.n_states * d.n_out);
   GW_LAUNCHED("zero_c128_kernel");
   const long nw = (long)nb * d.n_out * d.n_mesh;
+  // the weights depend on the band set only: once per set
+  for (int k = 0; k < d.n_k; ++k) {
+    ProfScope prof(s, "sigma_weights_kernel");
+    hipLaunchKernelGGL(sigma_weights_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, mesh, out, nb,
+                       d.eps + (size_t)k * nb, d.mu, C, wts + (size_t)k * nw);
+    GW_LAUNCHED("sigma_weights_kernel");
+  }
   bool u_tiled = false;
   double2* M64 = nullptr;
   double2* Y64 = nullptr;
+  double* part = nullptr;
   void* quad_ws = nullptr;
   if (d.precision == GW_FP64) {
     M64 = cv.take<double2>((size_t)d.N * nb);
     Y64 = cv.take<double2>((size_t)d.N * nb);
+    part = cv.take<double>((size_t)CD_CHUNKS64 * nb);
   } else {
     quad_ws = cv.take<char>(need.quad);
   }
@@ -388,12 +420,6 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
     for (int t = 0; t < d.n_k; ++t) {
       const int s2 = (s0 + t) % d.n_k;
       const double2* W = static_cast<const double2*>(d.W_host[t]);
-      {
-        ProfScope prof(s, "sigma_weights_kernel");
-        hipLaunchKernelGGL(sigma_weights_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, mesh, out, nb,
-                           d.eps + (size_t)s2 * nb, d.mu, C, wts);
-        GW_LAUNCHED("sigma_weights_kernel");
-      }
       if (d.precision == GW_FP64) {
         const double2* psi = static_cast<const double2*>(d.psi);
         const double2* pstate = psi + ((size_t)s0 * nb + n0) * d.R;
@@ -408,9 +434,13 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
                                W + (size_t)j * d.N * d.N, d.v, M64, Y64);
             GW_LAUNCHED("zgemm_shift_kernel");
           }
-          hipLaunchKernelGGL(coldot_f64_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, d.N, nb, M64, Y64,
-                             q + (size_t)j * nb);
+          const int rpc = (d.N + CD_CHUNKS64 - 1) / CD_CHUNKS64;
+          hipLaunchKernelGGL(coldot_f64_kernel, dim3((nb + 31) / 32, CD_CHUNKS64), dim3(256), 0, s, d.N, nb, M64, Y64,
+                             rpc, part);
           GW_LAUNCHED("coldot_f64_kernel");
+          hipLaunchKernelGGL(coldot_sum_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, CD_CHUNKS64, part,
+                             q + (size_t)j * nb);
+          GW_LAUNCHED("coldot_sum_kernel");
         }
       } else {
         const float2* psi = static_cast<const float2*>(d.psi);
@@ -421,8 +451,8 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
           return st;
         u_tiled = true;
       }
-      hipLaunchKernelGGL(sigma_contract_kernel, dim3(d.n_out), dim3(256), 0, s, nb, d.n_mesh, d.n_out, wts, q,
-                         sig + (size_t)si * d.n_out);
+      hipLaunchKernelGGL(sigma_contract_kernel, dim3(d.n_out), dim3(256), 0, s, nb, d.n_mesh, d.n_out,
+                         wts + (size_t)s2 * nw, q, sig + (size_t)si * d.n_out);
       GW_LAUNCHED("sigma_contract_kernel");
     }
   }

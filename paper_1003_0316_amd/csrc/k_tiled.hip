@@ -297,17 +297,40 @@ __global__ void tile_cols_kernel(int N, int nb, int nTb, int nst, const float2* 
   }
 }
 
-// q[n'] = Re sum_mu conj(M[mu][n']) Y[mu][n'] (FP64 accumulation).
-__global__ void coldot_f32_kernel(int N, int nb, const float2* __restrict__ M, const float2* __restrict__ Y, long ld,
-                                  double* __restrict__ q) {
+// q[n'] = Re sum_mu conj(M[mu][n']) Y[mu][n'] in two fixed-order passes: a
+// workgroup covers 32 columns and one chunk of rows (8 row groups of 32
+// lanes, combined in LDS), then the chunks are summed in order.
+constexpr int CD_CHUNKS = 16;
+
+__global__ __launch_bounds__(256) void coldot_f32_kernel(int N, int nb, const float2* __restrict__ M,
+                                                         const float2* __restrict__ Y, long ld, int rows_per_chunk,
+                                                         double* __restrict__ part) {
+  __shared__ double red[8][32];
+  const int cx = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  const int c = blockIdx.x * 32 + cx;
+  const int r0 = blockIdx.y * rows_per_chunk, r1 = min(N, r0 + rows_per_chunk);
+  double acc = 0.0;
+  if (c < nb)
+    for (int r = r0 + ry; r < r1; r += 8) {
+      const float2 m = M[(size_t)r * ld + c], y = Y[(size_t)r * ld + c];
+      acc += (double)m.x * (double)y.x + (double)m.y * (double)y.y;
+    }
+  red[ry][cx] = acc;
+  __syncthreads();
+  if (ry == 0 && c < nb) {
+    double t = red[0][cx];
+#pragma unroll
+    for (int g = 1; g < 8; ++g) t += red[g][cx];
+    part[(size_t)blockIdx.y * nb + c] = t;
+  }
+}
+
+__global__ void coldot_reduce_kernel(int nb, int chunks, const double* __restrict__ part, double* __restrict__ q) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nb) return;
-  double acc = 0.0;
-  for (int r = 0; r < N; ++r) {
-    const float2 m = M[(size_t)r * ld + c], y = Y[(size_t)r * ld + c];
-    acc += (double)m.x * (double)y.x + (double)m.y * (double)y.y;
-  }
-  q[c] = acc;
+  double t = 0.0;
+  for (int k = 0; k < chunks; ++k) t += part[(size_t)k * nb + c];
+  q[c] = t;
 }
 
 // --------------------------------------------------------------- GEMM core
@@ -1045,7 +1068,7 @@ int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Ch
 // column dots.
 struct SigmaDims {
   int nI, nstR, nstN, nbp, nTb;
-  size_t u_words, q_words, m_c64, mt_words, w_words;
+  size_t u_words, q_words, m_c64, mt_words, w_words, part;
   SigmaDims(int N, int R, int nb) {
     nI = cdiv(N, TR);
     nstR = cdiv(R, TK);
@@ -1057,10 +1080,11 @@ struct SigmaDims {
     m_c64 = (size_t)N * nbp;
     mt_words = (size_t)nTb * nstN * 2 * WD;
     w_words = (size_t)nI * nstN * 4 * WD;
+    part = (size_t)CD_CHUNKS * nb;
   }
   size_t bytes() const {
     return align_up(u_words * 4) + align_up(q_words * 4) + 2 * align_up(m_c64 * 8) + align_up(mt_words * 4) +
-           align_up(w_words * 4);
+           align_up(w_words * 4) + align_up(part * 8);
   }
 };
 
@@ -1077,6 +1101,8 @@ int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const
   float2* Y = cv.take<float2>(d.m_c64);
   uint32_t* Mt = cv.take<uint32_t>(d.mt_words);
   uint32_t* Ww = cv.take<uint32_t>(d.w_words);
+  double* part = cv.take<double>(d.part);
+  const int rows_per_chunk = cdiv(N, CD_CHUNKS);
   int st;
   TiledDims td(N, R, nb, 0);
   if (tile_u && (st = launch_tile_u(s, td, N, R, U, Uw)) != GW_OK) return st;
@@ -1116,9 +1142,12 @@ int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const
     b.M = Y;
     b.ldm = d.nbp;
     if ((st = launch_gemm<OUT_ROWS>(s, b, d.nI * b.nTj, "sigma_wm_kernel")) != GW_OK) return st;
-    hipLaunchKernelGGL(coldot_f32_kernel, dim3(cdiv(nb, 256)), dim3(256), 0, s, N, nb, M, Y, (long)d.nbp,
-                       q + (size_t)j * nb);
+    hipLaunchKernelGGL(coldot_f32_kernel, dim3(cdiv(nb, 32), CD_CHUNKS), dim3(256), 0, s, N, nb, M, Y, (long)d.nbp,
+                       rows_per_chunk, part);
     GW_LAUNCHED("coldot_f32_kernel");
+    hipLaunchKernelGGL(coldot_reduce_kernel, dim3(cdiv(nb, 256)), dim3(256), 0, s, nb, CD_CHUNKS, part,
+                       q + (size_t)j * nb);
+    GW_LAUNCHED("coldot_reduce_kernel");
   }
   return GW_OK;
 }
