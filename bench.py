@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--sigma", action="store_true",
                     help="measure the correlation self-energy instead (supercell workload: W for every momentum "
                          "transfer, then Sigma_c(i w) of the highest occupied and lowest unoccupied state)")
+    ap.add_argument("--real", action="store_true",
+                    help="measure the real-input (inversion-symmetric) path instead: the largest workload's shapes "
+                         "with real U and wave functions, explicit bands to the cutoff, against the complex path "
+                         "on the same pairs")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c5.json"),
                     help="measured per-launch HBM traffic of the dominant kernel (from rocprofv3 --pmc)")
     return ap.parse_args()
@@ -111,6 +115,85 @@ def traffic_driver(a) -> int:
     call.run()
     torch.cuda.synchronize()
     print(json.dumps({"traffic_driver": a.workload, "pairs": shp.n_occ * cutoff, "precision": a.precision}))
+    return 0
+
+
+def real_bench(a) -> int:
+    """Real inputs (the inversion-symmetric case): the largest workload's shapes
+    (N_k=4, N=6000, R=65536, 256 occupied bands, unoccupied bands 0..1499, 16
+    frequencies) with U and the wave functions replaced by their real parts.
+    Times one step of P (real split-BF16 path) + W, and the complex path on the
+    same inputs and pairs; prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import gwsynth
+    from paper_1003_0316_amd import binding as gw
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shp = gwsynth.SHAPES[a.workload]
+    cutoff = a.cutoff or shp.n_unocc_cut or shp.n_unocc
+    nb = shp.n_occ + cutoff
+    inp = gwsynth.generate_torch(shp, dev, band_limit=nb, log=log)
+    eps = np.ascontiguousarray(inp.eps[:, :nb])
+    U_r = inp.U.real.contiguous()
+    psi_r = inp.psi.real.contiguous()
+    U_c = U_r.to(torch.complex64)
+    psi_c = psi_r.to(torch.complex64)
+    v = torch.from_numpy(inp.v).to(dev)
+    mesh = inp.omega
+
+    def run(real):
+        call = gw.PolarizationCall(U_r if real else U_c, psi_r if real else psi_c, eps, mesh, shp.n_occ,
+                                   precision="split_bf16", real=real)
+        ws = gw.workspace(call.workspace_size(), dev, "real_bench")
+        for _ in range(a.warmup):
+            call.run(ws)
+            gw.gw_screen(call.P, v)
+        torch.cuda.synchronize()
+        gw.gw_profile_reset()
+        gw.gw_profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            call.run(ws)
+            W, info = gw.gw_screen(call.P, v)
+        e1.record()
+        torch.cuda.synchronize()
+        gw.gw_profile_enable(False)
+        ms = e0.elapsed_time(e1) / a.steps
+        kern = {k: gw.gw_profile_query(k) for k in ("project_bf16_kernel", "herk_bf16_kernel")}
+        P = call.P
+        return ms, kern, P
+
+    ms_r, kern_r, P_r = run(True)
+    imag_zero = bool(float(P_r.imag.abs().max()) == 0.0)
+    sym_err = float((P_r - P_r.transpose(1, 2)).abs().max())
+    del P_r
+    torch.cuda.empty_cache()
+    log(f"real path: {ms_r / 1e3:.3f} s/step")
+    ms_c, kern_c, P_c = run(False)
+    del P_c
+    log(f"complex path on the same inputs: {ms_c / 1e3:.3f} s/step")
+    T = shp.n_k * shp.n_occ * cutoff
+    n_pr, t_pr = kern_r["project_bf16_kernel"]
+    flops_real = 2.0 * shp.N * shp.R * T * a.steps          # one real multiply-add per (I, r, pair)
+    achieved = flops_real / (t_pr * 1e-3) / 1e12
+    out = {"metric": "P(q,iw) s/q-point, real inputs (inversion-symmetric), explicit bands to the cutoff",
+           "value": round(ms_r / 1e3, 4), "unit": "s/q-point", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": round(ms_r, 2), "higher_is_better": False, "dtype": "bf16x3 (split hi/lo) real, fp32 acc",
+           "data": "synthetic (seeded; paper-shaped; real parts of the generated U and wave functions)",
+           "config": {"workload": f"{a.workload} shapes, real inputs, unoccupied bands 0..{cutoff - 1}",
+                      "pairs": T, "step": "P (projection + accumulation) + W"},
+           "complex_path_same_inputs_s": round(ms_c / 1e3, 4), "speedup_vs_complex": round(ms_c / ms_r, 2),
+           "kernels_ms_per_step": {"real": {k: round(v[1] / a.steps, 1) for k, v in kern_r.items()},
+                                   "complex": {k: round(v[1] / a.steps, 1) for k, v in kern_c.items()}},
+           "roofline": {"bound": "mfma", "kernel": "project_bf16_kernel (real)", "achieved": round(achieved, 2),
+                        "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_TFLOPS["bf16"], 4), "traffic": None,
+                        "avg_launch_ms": round(t_pr / max(1, n_pr), 4), "launches": n_pr},
+           "p_imag_exactly_zero": imag_zero, "p_symmetry_max_abs": sym_err}
+    print(json.dumps(out))
     return 0
 
 
@@ -259,6 +342,8 @@ def main() -> int:
         return traffic_driver(a)
     if a.sigma:
         return sigma_bench(a)
+    if a.real:
+        return real_bench(a)
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build runs on one GPU only "
               f"(the k-point / occupied-band shards and the reduce-scatter of P over frequencies are "

@@ -105,7 +105,13 @@ int gw_project(void* stream, int precision, int N, int R, int n_occ, int n_unocc
  * Every pair summed must have eps_k[n] < eps_kq[n'] (insulator); otherwise
  * GW_ERR_INVALID_ARG.  omega_host entries must be finite and >= 0.
  * P is the full Hermitian matrix; its diagonal is stored with zero imaginary
- * part. */
+ * part.
+ *
+ * real_inputs = 1 (GW_SPLIT_BF16 only, else GW_ERR_UNSUPPORTED): U and psi
+ * are real float32 arrays of the same shapes -- the inversion-symmetric case,
+ * where a symmetrized basis makes the matrices real symmetric (Sec. "Mixed
+ * product basis", Eq. condition_inv; the text after Eq. polar_MB).  Every product and P are then real; P is returned as c128 with zero
+ * imaginary parts, and the contractions need a quarter of the MFMA work. */
 typedef struct gw_pol_desc {
   int precision;            /* gw_precision */
   int n_k;                  /* k-sets held in psi / eps */
@@ -126,6 +132,7 @@ typedef struct gw_pol_desc {
   double* P;                /* [n_omega][N][N] c128 output */
   int accumulate;           /* 0: P is overwritten; 1: the sum is added to P */
   int chunk_pairs;          /* transition pairs per chunk; 0 = library default */
+  int real_inputs;          /* 1: U and psi are real float32 (see above); 0: complex */
 } gw_pol_desc;
 
 int gw_polarization_workspace_size(const gw_pol_desc* desc_host, size_t* bytes_host);

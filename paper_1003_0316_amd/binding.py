@@ -50,6 +50,7 @@ class GwPolDesc(ctypes.Structure):
         ("eps", ctypes.c_void_p), ("eps_host", ctypes.POINTER(ctypes.c_double)),
         ("P", ctypes.c_void_p),
         ("accumulate", ctypes.c_int), ("chunk_pairs", ctypes.c_int),
+        ("real_inputs", ctypes.c_int),
     ]
 
 
@@ -218,9 +219,10 @@ class PolarizationCall:
     """Marshalled arguments of one gw_polarization call (keeps host arrays alive)."""
 
     def __init__(self, U, psi, eps_host, omega, n_occ, *, precision="fp64", eps_dev=None, P=None,
-                 k_list=None, kq=None, occ_range=None, unocc_range=None, accumulate=False, chunk_pairs=0):
+                 k_list=None, kq=None, occ_range=None, unocc_range=None, accumulate=False, chunk_pairs=0,
+                 real=False):
         prec = _prec(precision)
-        dt = _cdtype(prec)
+        dt = torch.float32 if real else _cdtype(prec)
         _dev_tensor(U, "U", dt)
         _dev_tensor(psi, "psi", dt)
         N, R = U.shape
@@ -265,6 +267,7 @@ class PolarizationCall:
         d.P = P.data_ptr()
         d.accumulate = 1 if accumulate else 0
         d.chunk_pairs = int(chunk_pairs)
+        d.real_inputs = 1 if real else 0
         self.desc = d
 
     def workspace_size(self) -> int:

@@ -50,7 +50,8 @@ Plan make_plan(const gw_pol_desc& d) {
   if (d.precision == GW_FP64) {
     pl.ws = align_up((size_t)d.N * pl.tc * 16) + align_up((size_t)d.n_omega * pl.tc * sizeof(double));
   } else {
-    pl.ws = mfma_pol_workspace(d.precision, d.N, d.R, pl.tc, d.n_omega);
+    pl.ws = d.real_inputs ? tiled_pol_workspace_real(d.N, d.R, pl.tc, d.n_omega)
+                          : mfma_pol_workspace(d.precision, d.N, d.R, pl.tc, d.n_omega);
   }
   return pl;
 }
@@ -59,6 +60,10 @@ int validate_desc(const gw_pol_desc* dp) {
   if (!dp) return fail(GW_ERR_INVALID_ARG, "gw_polarization: desc is NULL");
   const gw_pol_desc& d = *dp;
   if (!valid_precision(d.precision)) return fail(GW_ERR_INVALID_ARG, "gw_polarization: unknown precision");
+  if (d.real_inputs != 0 && d.real_inputs != 1)
+    return fail(GW_ERR_INVALID_ARG, "gw_polarization: real_inputs must be 0 or 1");
+  if (d.real_inputs && d.precision != GW_SPLIT_BF16)
+    return fail(GW_ERR_UNSUPPORTED, "gw_polarization: real inputs are supported with GW_SPLIT_BF16 only");
   if (d.n_k < 1 || d.N < 1 || d.R < 1 || d.n_occ < 1 || d.n_unocc < 1 || d.n_omega < 1)
     return fail(GW_ERR_INVALID_ARG, "gw_polarization: n_k, N, R, n_occ, n_unocc, n_omega must be >= 1");
   if (d.n_omega > kMaxOmega)
@@ -160,6 +165,10 @@ int gw_polarization_workspace_size(const gw_pol_desc* d, size_t* bytes) {
   if (d->N < 1 || d->R < 1 || d->n_omega < 1 || d->occ_end <= d->occ_begin || d->unocc_end <= d->unocc_begin)
     return fail(GW_ERR_INVALID_ARG, "gw_polarization_workspace_size: bad sizes or band ranges");
   if (d->chunk_pairs < 0) return fail(GW_ERR_INVALID_ARG, "gw_polarization: chunk_pairs < 0");
+  if (d->real_inputs != 0 && d->real_inputs != 1)
+    return fail(GW_ERR_INVALID_ARG, "gw_polarization: real_inputs must be 0 or 1");
+  if (d->real_inputs && d->precision != GW_SPLIT_BF16)
+    return fail(GW_ERR_UNSUPPORTED, "gw_polarization: real inputs are supported with GW_SPLIT_BF16 only");
   *bytes = make_plan(*d).ws;
   return GW_OK;
 }
@@ -218,7 +227,8 @@ int gw_polarization(void* stream, const gw_pol_desc* dp, void* ws, size_t ws_byt
       if ((st = launch_herk_f64(s, d.N, c.pairs(), M, c.pairs(), w, d.n_omega, P)) != GW_OK) return st;
     }
   } else {
-    st = mfma_polarization(s, d, chunks, pl.tc, om, ws);
+    st = d.real_inputs ? tiled_polarization_real(s, d, chunks, pl.tc, om, ws)
+                       : mfma_polarization(s, d, chunks, pl.tc, om, ws);
     if (st != GW_OK) return st;
   }
   return launch_hermitian_mirror(s, d.N, d.n_omega, P);

@@ -26,6 +26,11 @@ int tiled_project(hipStream_t s, int N, int R, int n_occ, int n_unocc, const flo
 int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
                        const OmegaList& om, void* ws);
 
+// Real inputs (inversion-symmetric case), split BF16 (k_tiled.hip).
+size_t tiled_pol_workspace_real(int N, int R, int tc, int n_omega);
+int tiled_polarization_real(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
+                            const OmegaList& om, void* ws);
+
 // Correlation self-energy, split-BF16 quadratic forms (k_tiled.hip).
 size_t tiled_sigma_workspace(int N, int R, int nb);
 int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const float2* U, bool tile_u,

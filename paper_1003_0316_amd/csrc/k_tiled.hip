@@ -34,6 +34,7 @@
 #include "gw_mfma.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace gw {
 namespace {
@@ -331,6 +332,112 @@ __global__ void coldot_reduce_kernel(int nb, int chunks, const double* __restric
   double t = 0.0;
   for (int k = 0; k < chunks; ++k) t += part[(size_t)k * nb + c];
   q[c] = t;
+}
+
+// ------------------------------------------- real operands (inversion symmetry)
+// With real U and real wave functions every product is real: one word holds
+// two consecutive real k values, a block-stage covers 32 k, and the operands
+// need only hi and lo (no sign or swap patterns).
+__device__ inline void split_pair(float a, float b, uint32_t& hi, uint32_t& lo) {
+  float ah, al, bh, bl;
+  split2(a, ah, al);
+  split2(b, bh, bl);
+  hi = pack_bf16(ah, bh);
+  lo = pack_bf16(al, bl);
+}
+
+// U (float [N][R]) -> A-side words [nI][nst][2][WD] (hi, lo), zero outside.
+__global__ void tile_u_real_kernel(int N, int R, int nI, int nst, const float* __restrict__ U,
+                                   uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nI * nst * 4 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % TR);
+    const int sh = (int)((e / TR) % 4);
+    const size_t bs = e / (4 * TR);
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int I = blk * TR + row;
+    const int r0 = st * 2 * TK + sh * 8;
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + 2 * j;
+      const float a = (I < N && r < R) ? U[(size_t)I * R + r] : 0.f;
+      const float b = (I < N && r + 1 < R) ? U[(size_t)I * R + r + 1] : 0.f;
+      split_pair(a, b, hw[j], lw[j]);
+    }
+    uint32_t* o = out + bs * 2 * WD + lane_off(sh, row);
+    *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    *reinterpret_cast<uint4*>(o + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+  }
+}
+
+// Real pair products F_t = psi_n psi_n' -> B-side words [nT][nst][2][WD].
+__global__ void pair_product_real_kernel(int R, int nst, int nT, const float* __restrict__ po,
+                                         const float* __restrict__ pu, int nu, long tb, int T,
+                                         uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nT * nst * 4 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(e % TR);
+    const int sh = (int)((e / TR) % 4);
+    const size_t bs = e / (4 * TR);
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int t = blk * TR + col;
+    const int r0 = st * 2 * TK + sh * 8;
+    const float* a = nullptr;
+    const float* b = nullptr;
+    if (t < T) {
+      const long g = tb + t;
+      a = po + (size_t)(g / nu) * R;
+      b = pu + (size_t)(g % nu) * R;
+    }
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + 2 * j;
+      const float f0 = (a && r < R) ? a[r] * b[r] : 0.f;
+      const float f1 = (a && r + 1 < R) ? a[r + 1] * b[r + 1] : 0.f;
+      split_pair(f0, f1, hw[j], lw[j]);
+    }
+    uint32_t* o = out + bs * 2 * WD + lane_off(sh, col);
+    *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    *reinterpret_cast<uint4*>(o + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+  }
+}
+
+// Real M (tiled [nI][nstT][4][TR][8] floats) -> X_j = s_j M as words
+// [n_omega][nIe][nstT][2][WD] (hi, lo); blocks in [nI, nIe) are zero.
+__global__ void scale_split_real_kernel(int nI, int nIe, int nstT, int Tp, int n_omega, const float* __restrict__ Mt,
+                                        const float* __restrict__ sw, uint32_t* __restrict__ X) {
+  const size_t total = (size_t)nIe * nstT * 4 * TR;
+  const size_t xstride = (size_t)nIe * nstT * 2 * WD;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % TR);
+    const int sh = (int)((e / TR) % 4);
+    const size_t bs = e / (4 * TR);
+    const int st = (int)(bs % nstT), blk = (int)(bs / nstT);
+    float m[8];
+    if (blk < nI) {
+      const float4* src = reinterpret_cast<const float4*>(Mt + e * 8);
+      const float4 p = src[0], q = src[1];
+      m[0] = p.x; m[1] = p.y; m[2] = p.z; m[3] = p.w; m[4] = q.x; m[5] = q.y; m[6] = q.z; m[7] = q.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) m[j] = 0.f;
+    }
+    const int t0 = st * 2 * TK + sh * 8;
+    uint32_t* o = X + bs * 2 * WD + lane_off(sh, row);
+    for (int jw = 0; jw < n_omega; ++jw) {
+      const float4 s0 = *reinterpret_cast<const float4*>(sw + (size_t)jw * Tp + t0);
+      const float4 s1 = *reinterpret_cast<const float4*>(sw + (size_t)jw * Tp + t0 + 4);
+      const float sc[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+      uint32_t hw[4], lw[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) split_pair(sc[2 * j] * m[2 * j], sc[2 * j + 1] * m[2 * j + 1], hw[j], lw[j]);
+      uint32_t* oj = o + (size_t)jw * xstride;
+      *reinterpret_cast<uint4*>(oj) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      *reinterpret_cast<uint4*>(oj + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
+  }
 }
 
 // --------------------------------------------------------------- GEMM core
@@ -703,40 +810,58 @@ __global__ __launch_bounds__(GT, 1) void gemm_bf16x3_kernel(GemmArgs g) {
 // wave's waits on LDS, barriers and loads overlap the other wave's MFMAs.
 constexpr int GT8 = 512;
 
+// AW A-side words per block-stage: 4 for complex operands (conj|x, swap|-ix;
+// hi, lo), 2 for real ones (hi, lo; a dword then holds two consecutive real
+// k values, so a block-stage covers 32 real k).
+template <int AW>
 struct Staged8 {
-  uint4 a0, a1, a2, a3, b0, b1, c0, c1;
+  uint4 a[AW];
+  uint4 b0, b1, c0, c1;
 };
 
-__device__ __forceinline__ void stage_load8(Staged8& r, const uint32_t* Ap, const uint32_t* B0, const uint32_t* B1,
-                                            size_t b_step, int st, int tid) {
-  const uint32_t* a = Ap + (size_t)st * 4 * WD;
+template <int AW>
+__device__ __forceinline__ void stage_load8(Staged8<AW>& r, const uint32_t* Ap, const uint32_t* B0,
+                                            const uint32_t* B1, size_t b_step, int st, int tid) {
+  const uint32_t* a = Ap + (size_t)st * AW * WD;
   const uint32_t* b0 = B0 + (size_t)st * b_step;
   const uint32_t* b1 = B1 + (size_t)st * b_step;
   auto ld = [&](const uint32_t* p, int q) __attribute__((always_inline)) {
     return *reinterpret_cast<const uint4*>(p + (q * GT8 + tid) * 4);
   };
-  r.a0 = ld(a, 0); r.a1 = ld(a, 1); r.a2 = ld(a, 2); r.a3 = ld(a, 3);
+#pragma unroll
+  for (int q = 0; q < AW; ++q) r.a[q] = ld(a, q);
   r.b0 = ld(b0, 0); r.b1 = ld(b0, 1); r.c0 = ld(b1, 0); r.c1 = ld(b1, 1);
 }
 
-__device__ __forceinline__ void stage_store8(const Staged8& r, uint32_t* L, int part, int tid) {
+// LDS stage: A words at [0, AW WD), B half c word q at (AW + 2 c + q) WD.
+template <int AW>
+__device__ __forceinline__ void stage_store8(const Staged8<AW>& r, uint32_t* L, int part, int tid) {
   auto st = [&](uint32_t* p, int q, uint4 v) __attribute__((always_inline)) {
     *reinterpret_cast<uint4*>(p + (q * GT8 + tid) * 4) = v;
   };
   if (part == 0) {
-    st(L, 0, r.a0); st(L, 1, r.a1); st(L, 2, r.a2); st(L, 3, r.a3);
+#pragma unroll
+    for (int q = 0; q < AW; ++q) st(L, q, r.a[q]);
   } else {
-    st(L + 4 * WD, 0, r.b0); st(L + 4 * WD, 1, r.b1); st(L + 6 * WD, 0, r.c0); st(L + 6 * WD, 1, r.c1);
+    st(L + AW * WD, 0, r.b0); st(L + AW * WD, 1, r.b1); st(L + (AW + 2) * WD, 0, r.c0); st(L + (AW + 2) * WD, 1, r.c1);
   }
 }
 
+template <int AW>
 struct Frags8 {
-  uint4 a[4][2];
+  uint4 a[AW][2];
   uint4 b[2][2];
 };
 
-template <int OUT>
+template <bool REAL>
+constexpr size_t gemm8_lds_bytes() {
+  return 2 * (size_t)((REAL ? 2 : 4) + 4) * WD * sizeof(uint32_t);
+}
+
+template <int OUT, bool REAL = false>
 __global__ __launch_bounds__(GT8, 1) void gemm8_bf16x3_kernel(GemmArgs g) {
+  constexpr int AW = REAL ? 2 : 4;
+  constexpr int STAGE = (AW + 4) * WD;
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   int ti, tj, jw;
   decode_tile<OUT>(g, ti, tj, jw);
@@ -761,20 +886,20 @@ __global__ __launch_bounds__(GT8, 1) void gemm8_bf16x3_kernel(GemmArgs g) {
         ci[a][b][v] = 0.f;
       }
 
-  Staged8 r;
-  stage_load8(r, Ap, B0, B1, b_step, 0, tid);
-  stage_store8(r, lds, 0, tid);
-  stage_store8(r, lds, 1, tid);
-  stage_load8(r, Ap, B0, B1, b_step, min(1, g.nst - 1), tid);
+  Staged8<AW> r;
+  stage_load8<AW>(r, Ap, B0, B1, b_step, 0, tid);
+  stage_store8<AW>(r, lds, 0, tid);
+  stage_store8<AW>(r, lds, 1, tid);
+  stage_load8<AW>(r, Ap, B0, B1, b_step, min(1, g.nst - 1), tid);
   lds_barrier();
   for (int st = 0; st < g.nst; ++st) {
-    const uint32_t* L = lds + (st & 1) * LDS_STAGE;
-    uint32_t* Ln = lds + ((st + 1) & 1) * LDS_STAGE;
+    const uint32_t* L = lds + (st & 1) * STAGE;
+    uint32_t* Ln = lds + ((st + 1) & 1) * STAGE;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      Frags8 f;
+      Frags8<AW> f;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < AW; ++q)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
           f.a[q][rb] = *reinterpret_cast<const uint4*>(L + q * WD + lane_off(s * 2 + h, wm * 64 + rb * 32 + l32));
@@ -783,29 +908,32 @@ __global__ __launch_bounds__(GT8, 1) void gemm8_bf16x3_kernel(GemmArgs g) {
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
           f.b[q][cb] =
-              *reinterpret_cast<const uint4*>(L + (4 + 2 * half + q) * WD + lane_off(s * 2 + h, c0 + cb * 32 + l32));
+              *reinterpret_cast<const uint4*>(L + (AW + 2 * half + q) * WD + lane_off(s * 2 + h, c0 + cb * 32 + l32));
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
           cr[rb][cb] = mma(f.a[0][rb], f.b[0][cb], cr[rb][cb]);
-          ci[rb][cb] = mma(f.a[2][rb], f.b[0][cb], ci[rb][cb]);
+          if constexpr (!REAL) ci[rb][cb] = mma(f.a[2][rb], f.b[0][cb], ci[rb][cb]);
           cr[rb][cb] = mma(f.a[0][rb], f.b[1][cb], cr[rb][cb]);
-          ci[rb][cb] = mma(f.a[2][rb], f.b[1][cb], ci[rb][cb]);
+          if constexpr (!REAL) ci[rb][cb] = mma(f.a[2][rb], f.b[1][cb], ci[rb][cb]);
           cr[rb][cb] = mma(f.a[1][rb], f.b[0][cb], cr[rb][cb]);
-          ci[rb][cb] = mma(f.a[3][rb], f.b[0][cb], ci[rb][cb]);
+          if constexpr (!REAL) ci[rb][cb] = mma(f.a[3][rb], f.b[0][cb], ci[rb][cb]);
         }
       // the staged next stage goes to the idle buffer, half per step; after
       // the second half the registers take the stage after next (past the
       // end: the final stage again, in bounds, into a buffer never read)
-      stage_store8(r, Ln, s, tid);
-      if (s == 1) stage_load8(r, Ap, B0, B1, b_step, min(st + 2, g.nst - 1), tid);
+      stage_store8<AW>(r, Ln, s, tid);
+      if (s == 1) stage_load8<AW>(r, Ap, B0, B1, b_step, min(st + 2, g.nst - 1), tid);
     }
     lds_barrier();
   }
 
   if constexpr (OUT == OUT_HERK) {
-    float2* E = reinterpret_cast<float2*>(lds);   // [128][128], one column half at a time
+    // one 128 x 128 column half at a time: complex FP32 (128 KB) or, for
+    // real operands, real FP32 (64 KB, inside the 96 KB of the real core)
+    using ET = typename std::conditional<REAL, float, float2>::type;
+    ET* E = reinterpret_cast<ET*>(lds);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       if (half == c) {
@@ -816,7 +944,10 @@ __global__ __launch_bounds__(GT8, 1) void gemm8_bf16x3_kernel(GemmArgs g) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
               const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-              E[row * 128 + c0 + cb * 32 + l32] = make_float2(cr[rb][cb][v], ci[rb][cb][v]);
+              if constexpr (REAL)
+                E[row * 128 + c0 + cb * 32 + l32] = cr[rb][cb][v];
+              else
+                E[row * 128 + c0 + cb * 32 + l32] = make_float2(cr[rb][cb][v], ci[rb][cb][v]);
             }
       }
       __syncthreads();
@@ -825,11 +956,15 @@ __global__ __launch_bounds__(GT8, 1) void gemm8_bf16x3_kernel(GemmArgs g) {
       for (int e = tid; e < 128 * 128; e += GT8) {
         const int gi = ti * TM + (e >> 7), gj = tj * TN + c * 128 + (e & 127);
         if (gi < g.N && gj <= gi) {
-          const float2 x = E[e];
           double2* p = Pj + (size_t)gi * g.N + gj;
           double2 y = *p;
-          y.x -= (double)x.x;
-          y.y -= (double)x.y;
+          if constexpr (REAL) {
+            y.x -= (double)E[e];
+          } else {
+            const float2 x = E[e];
+            y.x -= (double)x.x;
+            y.y -= (double)x.y;
+          }
           *p = y;
         }
       }
@@ -845,12 +980,19 @@ __global__ __launch_bounds__(GT8, 1) void gemm8_bf16x3_kernel(GemmArgs g) {
       for (int v = 0; v < 16; ++v) {
         const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         const int col = wn * 64 + cb * 32 + l32;
-        const float re = cr[rb][cb][v], im = ci[rb][cb][v];
+        const float re = cr[rb][cb][v], im = REAL ? 0.f : ci[rb][cb][v];
         if constexpr (OUT == OUT_TILED) {
           const int t = tj * TN + col;
-          const size_t bs = (size_t)ti * g.nst_out + t / TK;
-          const int kk = t % TK;
-          g.M[(bs * 4 + (kk >> 2)) * TR * 4 + row * 4 + (kk & 3)] = make_float2(re, im);
+          if constexpr (REAL) {
+            // real M for the accumulation operands: [nI][T/32][4][TR][8] floats
+            const size_t bs = (size_t)ti * g.nst_out + t / (2 * TK);
+            const int kk = t % (2 * TK);
+            reinterpret_cast<float*>(g.M)[((bs * 4 + (kk >> 3)) * TR + row) * 8 + (kk & 7)] = re;
+          } else {
+            const size_t bs = (size_t)ti * g.nst_out + t / TK;
+            const int kk = t % TK;
+            g.M[(bs * 4 + (kk >> 2)) * TR * 4 + row * 4 + (kk & 3)] = make_float2(re, im);
+          }
         } else {
           const int gi = ti * TM + row, gt = tj * TN + col;
           if (gi < g.N && gt < g.T) g.M[(size_t)gi * g.ldm + gt] = make_float2(re, im);
@@ -926,16 +1068,17 @@ int launch_gemm_as(hipStream_t s, const GemmArgs& a, int grid, const char* name)
   return GW_OK;
 }
 
-template <int OUT>
+template <int OUT, bool REAL = false>
 int launch_gemm8(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
   static int attr = 0;
+  constexpr size_t lds_bytes = gemm8_lds_bytes<REAL>();
   if (!attr) {
-    GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm8_bf16x3_kernel<OUT>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds));
+    GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm8_bf16x3_kernel<OUT, REAL>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     attr = 1;
   }
   ProfScope prof(s, name);
-  hipLaunchKernelGGL((gemm8_bf16x3_kernel<OUT>), dim3(grid), dim3(GT8), kGemmLds, s, a);
+  hipLaunchKernelGGL((gemm8_bf16x3_kernel<OUT, REAL>), dim3(grid), dim3(GT8), lds_bytes, s, a);
   GW_LAUNCHED("gemm8_bf16x3_kernel");
   return GW_OK;
 }
@@ -1057,6 +1200,100 @@ int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Ch
     b.N = d.N;
     b.P = reinterpret_cast<double2*>(d.P);
     if ((st = launch_gemm<OUT_HERK>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")) != GW_OK) return st;
+  }
+  return GW_OK;
+}
+
+// ---------------------------------------------------------- real path
+// Real U and wave functions (the inversion-symmetric case): P is real
+// symmetric; every contraction runs on the real form of the GEMM core (a
+// quarter of the complex path's MFMA work).
+struct RealDims {
+  int nI, nIe, nstR, Tp, nT, nstT;
+  size_t u_words, q_words, m_f32, x_words, sw_f32;
+  RealDims(int N, int R, int T, int n_omega) {
+    nI = cdiv(N, TR);
+    nIe = (nI + 1) & ~1;
+    nstR = cdiv(R, 2 * TK);
+    Tp = cdiv(T, TN) * TN;
+    nT = Tp / TR;
+    nstT = Tp / (2 * TK);
+    u_words = (size_t)nI * nstR * 2 * WD;
+    q_words = (size_t)nT * nstR * 2 * WD;
+    m_f32 = (size_t)nI * nstT * 4 * TR * 8;
+    x_words = (size_t)n_omega * nIe * nstT * 2 * WD;
+    sw_f32 = (size_t)n_omega * Tp;
+  }
+  size_t bytes() const {
+    return align_up(u_words * 4) + align_up(q_words * 4) + align_up(m_f32 * 4) + align_up(x_words * 4) +
+           align_up(sw_f32 * 4);
+  }
+};
+
+size_t tiled_pol_workspace_real(int N, int R, int tc, int n_omega) { return RealDims(N, R, tc, n_omega).bytes(); }
+
+int tiled_polarization_real(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
+                            const OmegaList& om, void* ws) {
+  RealDims dm(d.N, d.R, tc, d.n_omega);
+  Carver cv(ws);
+  uint32_t* Uw = cv.take<uint32_t>(dm.u_words);
+  uint32_t* Q = cv.take<uint32_t>(dm.q_words);
+  float* Mt = cv.take<float>(dm.m_f32);
+  uint32_t* X = cv.take<uint32_t>(dm.x_words);
+  float* sw = cv.take<float>(dm.sw_f32);
+  const float* psi = static_cast<const float*>(d.psi);
+  const int nb = d.n_occ + d.n_unocc;
+  hipLaunchKernelGGL(tile_u_real_kernel, dim3(stream_blocks((size_t)dm.nI * dm.nstR * 4 * TR)), dim3(256), 0, s, d.N,
+                     d.R, dm.nI, dm.nstR, static_cast<const float*>(d.U), Uw);
+  GW_LAUNCHED("tile_u_real_kernel");
+  const int n_tiles = count_lower_tiles(dm.nI);
+  int st;
+  for (const Chunk& c : chunks) {
+    RealDims cd(d.N, d.R, c.T, d.n_omega);
+    const float* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
+    const float* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
+    hipLaunchKernelGGL(weights_sqrt_kernel, dim3(cdiv(cd.Tp, 256)), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om, cd.Tp,
+                       sw);
+    GW_LAUNCHED("weights_sqrt_kernel");
+    {
+      ProfScope prof(s, "pair_product_kernel");
+      hipLaunchKernelGGL(pair_product_real_kernel, dim3(stream_blocks((size_t)cd.nT * cd.nstR * 4 * TR)), dim3(256), 0,
+                         s, d.R, cd.nstR, cd.nT, po, pu, c.nu, c.tb, c.T, Q);
+      GW_LAUNCHED("pair_product_real_kernel");
+    }
+    GemmArgs a{};
+    a.A = Uw;
+    a.B = Q;
+    a.b_words = 2;
+    a.nst = cd.nstR;
+    a.a_bstride = (size_t)cd.nstR * 2 * WD;
+    a.b_bstride = (size_t)cd.nstR * 2 * WD;
+    a.nI = cd.nI;
+    a.nTj = cd.Tp / TN;
+    a.N = d.N;
+    a.T = c.T;
+    a.M = reinterpret_cast<float2*>(Mt);
+    a.nst_out = cd.nstT;
+    if ((st = launch_gemm8<OUT_TILED, true>(s, a, cd.nI * a.nTj, "project_bf16_kernel")) != GW_OK) return st;
+    {
+      ProfScope prof(s, "scale_split_kernel");
+      hipLaunchKernelGGL(scale_split_real_kernel, dim3(stream_blocks((size_t)cd.nIe * cd.nstT * 4 * TR)), dim3(256), 0,
+                         s, cd.nI, cd.nIe, cd.nstT, cd.Tp, d.n_omega, Mt, sw, X);
+      GW_LAUNCHED("scale_split_real_kernel");
+    }
+    GemmArgs b{};
+    b.A = X;
+    b.B = X;
+    b.b_words = 2;
+    b.nst = cd.nstT;
+    b.a_bstride = (size_t)cd.nstT * 2 * WD;
+    b.b_bstride = (size_t)cd.nstT * 2 * WD;
+    b.omega_stride = (size_t)cd.nIe * cd.nstT * 2 * WD;
+    b.nI = cd.nI;
+    b.n_tiles = n_tiles;
+    b.N = d.N;
+    b.P = reinterpret_cast<double2*>(d.P);
+    if ((st = launch_gemm8<OUT_HERK, true>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")) != GW_OK) return st;
   }
   return GW_OK;
 }

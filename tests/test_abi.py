@@ -212,3 +212,15 @@ def test_sigma_workspace_and_null_w(b):
     assert b.lib().gw_sigma_c(None, ctypes.byref(d), None, 0) == -3       # no workspace
     keep["W"][1] = None
     assert b.lib().gw_sigma_c_workspace_size(ctypes.byref(d), ctypes.byref(out)) == -1
+
+
+def test_real_inputs_validation(b):
+    d, keep = _desc(b, precision=0)
+    d.real_inputs = 1
+    out = ctypes.c_size_t(0)
+    assert b.lib().gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(out)) == -2   # FP64: unsupported
+    d.precision = 2
+    d.real_inputs = 2
+    assert b.lib().gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(out)) == -1
+    d.real_inputs = 1
+    assert b.lib().gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 0 and out.value > 0

@@ -316,3 +316,17 @@ def test_hand_worked_examples():
         W = orc.screened_interaction(P, np.array(c["v"]))
         Wexp = np.array(c["W_re"]) + 1j * np.array(c["W_im"])
         np.testing.assert_allclose(W, Wexp, rtol=1e-13, atol=1e-15)
+
+
+def test_real_inputs_give_real_symmetric_P():
+    """With a real basis and real wave functions (the inversion-symmetric case
+    of Eq. condition_inv) the matrix elements are real and P is real
+    symmetric (text after Eq. polar_MB)."""
+    rng = np.random.default_rng(21)
+    n_k, N, R, n_occ, n_unocc = 2, 5, 12, 2, 3
+    U = rng.normal(size=(N, R)).astype(np.complex128)
+    psi = rng.normal(size=(n_k, n_occ + n_unocc, R)).astype(np.complex128)
+    eps = np.tile(np.array([-0.4, -0.1, 0.2, 0.5, 1.1]), (n_k, 1))
+    P = orc.polarization(U, psi, eps, [0.0, 0.7], n_occ)
+    assert np.all(P.imag == 0.0)
+    assert np.allclose(P, np.transpose(P, (0, 2, 1)), rtol=0, atol=1e-13 * np.abs(P).max())
