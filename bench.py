@@ -66,6 +66,9 @@ def parse():
                     help="measure the real-input (inversion-symmetric) path instead: the largest workload's shapes "
                          "with real U and wave functions, explicit bands to the cutoff, against the complex path "
                          "on the same pairs")
+    ap.add_argument("--mpb", action="store_true",
+                    help="basis optimization study instead: Sigma_c and time against the Coulomb-eigenvalue "
+                         "threshold v_min on the training-run shapes")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c5.json"),
                     help="measured per-launch HBM traffic of the dominant kernel (from rocprofv3 --pmc)")
     return ap.parse_args()
@@ -115,6 +118,76 @@ def traffic_driver(a) -> int:
     call.run()
     torch.cuda.synchronize()
     print(json.dumps({"traffic_driver": a.workload, "pairs": shp.n_occ * cutoff, "precision": a.precision}))
+    return 0
+
+
+def mpb_bench(a) -> int:
+    """Optimization of the product basis (keep v_mu >= v_min) on the
+    training-run shapes (N_k=4, N=1000, R=8192, 64 + 1500 bands, 16
+    frequencies): for each threshold, W for all 4 momentum transfers and
+    Sigma_c(i w) of the highest occupied and lowest unoccupied band of set 0,
+    split BF16 throughout; errors against the full basis.  One JSON line."""
+    import numpy as np
+    import torch
+
+    import gwsynth
+    from paper_1003_0316_amd import binding as gw
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shp = gwsynth.SHAPES["c4train"]
+    inp = gwsynth.generate_torch(shp, dev, log=log)
+    v_full = torch.from_numpy(inp.v).to(dev)
+    mesh = inp.omega
+    n_k = shp.n_k
+    mu = 0.5 * (inp.eps[:, :shp.n_occ].max() + inp.eps[:, shp.n_occ:].min())
+    states = [(0, shp.n_occ - 1), (0, shp.n_occ)]
+    v_sorted = np.sort(inp.v)[::-1]
+    rows = []
+    ref = None
+    # warm-up: one full-basis pass (library set-up and workspaces outside the timings)
+    Ws = []
+    for t in range(n_k):
+        kq = (np.arange(n_k) + t) % n_k
+        P = gw.gw_polarization(inp.U, inp.psi, inp.eps, mesh, shp.n_occ, precision="split_bf16", kq=kq)
+        Ws.append(gw.gw_screen(P, v_full)[0])
+        del P
+    gw.gw_sigma_c(inp.U, inp.psi, inp.eps, Ws, v_full, mesh, mesh, states, mu, precision="split_bf16")
+    torch.cuda.synchronize()
+    del Ws
+    for frac in (1.0, 0.8, 0.6, 0.45, 0.3, 0.2):
+        n_keep = max(1, int(round(frac * shp.N)))
+        v_min = 0.0 if frac == 1.0 else float(v_sorted[n_keep - 1])
+        torch.cuda.synchronize()
+        t0 = time.time()
+        U, v, _ = gw.gw_basis_select(inp.U, v_full, v_min)
+        Ws = []
+        for t in range(n_k):
+            kq = (np.arange(n_k) + t) % n_k
+            P = gw.gw_polarization(U, inp.psi, inp.eps, mesh, shp.n_occ, precision="split_bf16", kq=kq)
+            W, info = gw.gw_screen(P, v)
+            del P
+            Ws.append(W)
+        sig = gw.gw_sigma_c(U, inp.psi, inp.eps, Ws, v, mesh, mesh, states, mu, precision="split_bf16")
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        s = sig.cpu().numpy()
+        if ref is None:
+            ref = s
+        err = float(np.max(np.abs(s - ref)) / np.max(np.abs(ref)))
+        gap = float((s[1, 0] - s[0, 0]).real - (ref[1, 0] - ref[0, 0]).real)
+        rows.append({"v_min": v_min, "sqrt_4pi_over_v_min": (float(np.sqrt(4 * np.pi / v_min)) if v_min > 0 else None),
+                     "rank": int(U.shape[0]), "seconds": round(dt, 3), "sigma_rel_err": err,
+                     "gap_sigma_change_Ha": gap, "gap_sigma_change_eV": gap * 27.211386})
+        log(f"v_min {v_min:.3f}: rank {U.shape[0]}, {dt:.2f} s, Sigma rel err {err:.2e}, gap change {gap * 27.211:.4f} eV")
+        del Ws, sig, U, v
+        torch.cuda.empty_cache()
+    out = {"metric": "Sigma_c(i w) error and time vs the Coulomb-eigenvalue threshold v_min",
+           "unit": "s per (W for all transfers + Sigma_c of 2 states)", "n_gpus": 1,
+           "data": "synthetic (seeded; training-run shapes)",
+           "config": {"workload": "N_k=4, N=1000, R=8192, 64 occ + 1500 unocc bands, 16 imaginary frequencies",
+                      "states": states, "precision": "split_bf16"},
+           "rows": rows}
+    print(json.dumps(out))
     return 0
 
 
@@ -344,6 +417,8 @@ def main() -> int:
         return sigma_bench(a)
     if a.real:
         return real_bench(a)
+    if a.mpb:
+        return mpb_bench(a)
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build runs on one GPU only "
               f"(the k-point / occupied-band shards and the reduce-scatter of P over frequencies are "

@@ -237,6 +237,24 @@ int gw_surrogate_judge(void* stream, const gw_surr_desc* d_host, const float* Y,
                        int n_sample, const int* sample_k_host, const int* sample_occ_host, double* err, void* ws,
                        size_t ws_bytes);
 
+/* ------------------------------------------------ basis optimization (v_min)
+ * Sec. "Optimization of the MPB": only the Coulomb eigenfunctions with
+ * eigenvalue v_mu >= v_min are kept (v_min = 0 restores the full basis).  With
+ * the basis in the Coulomb eigenbasis (diagonal v) this compacts the rows of U
+ * and the entries of v, preserving their order; the reduced U and v are then
+ * passed to gw_polarization / gw_screen / gw_sigma_c unchanged.
+ *
+ * gw_basis_select_count: host-only; n_keep_host = #{i : v_host[i] >= v_min}.
+ * gw_basis_select: U [N][R] device rows of elem_bytes-byte elements (4 real
+ * float, 8 c64, 16 c128), v [N] device; writes U_out [n_keep][R], v_out
+ * [n_keep] and src_of_dst [n_keep] (device: original row of each kept row).
+ * n_keep must be the count above (the device recomputes the selection from
+ * v, which must hold the same values as v_host); with n_keep = 0 nothing is
+ * written and the output pointers may be NULL.  Asynchronous on stream. */
+int gw_basis_select_count(int N, const double* v_host, double v_min, int* n_keep_host);
+int gw_basis_select(void* stream, int N, int R, int elem_bytes, const void* U, const double* v, double v_min,
+                    int n_keep, void* U_out, double* v_out, int* src_of_dst);
+
 /* ------------------------------------------------- correlation self-energy
  * Diagonal correlation self-energy on the imaginary axis, Eq. SEc_AC (the
  * analytic continuation of Eq. SEc_MB), for a list of states (set s, band n):

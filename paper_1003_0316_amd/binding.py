@@ -120,13 +120,16 @@ _lib.gw_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(_ci), ctypes.P
 _lib.gw_sigma_c_workspace_size.argtypes = [ctypes.POINTER(GwSigmaDesc), ctypes.POINTER(_sz)]
 _lib.gw_sigma_c.argtypes = [_vp, ctypes.POINTER(GwSigmaDesc), _vp, _sz]
 
+_lib.gw_basis_select_count.argtypes = [_ci, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.POINTER(_ci)]
+_lib.gw_basis_select.argtypes = [_vp, _ci, _ci, _ci, _vp, _vp, ctypes.c_double, _ci, _vp, _vp, _vp]
+
 EXPORTED = ("gw_last_error", "gw_version", "gw_project_workspace_size", "gw_project",
             "gw_polarization_workspace_size", "gw_polarization", "gw_screen_workspace_size", "gw_screen",
             "gw_profile_enable", "gw_profile_reset", "gw_profile_query",
             "gw_mlp_sizes", "gw_mlp_sync_bf16", "gw_mlp_forward", "gw_mlp_loss", "gw_mlp_workspace_size",
             "gw_mlp_backward", "gw_mlp_adam_step", "gw_surrogate_workspace_size", "gw_surrogate_features",
             "gw_surrogate_targets", "gw_surrogate_apply", "gw_surrogate_judge", "gw_set_tuning",
-            "gw_sigma_c_workspace_size", "gw_sigma_c")
+            "gw_sigma_c_workspace_size", "gw_sigma_c", "gw_basis_select_count", "gw_basis_select")
 
 
 def lib():
@@ -567,4 +570,23 @@ def gw_sigma_c(U, psi, eps_host, W_by_transfer, v, mesh, omega_out, states, mu, 
     ws = kw.pop("ws", None)
     stream = kw.pop("stream", None)
     return SigmaCall(U, psi, eps_host, W_by_transfer, v, mesh, omega_out, states, mu, **kw).run(ws, stream)
+
+
+def gw_basis_select(U: torch.Tensor, v: torch.Tensor, v_min: float, stream=None):
+    """Keep the basis functions with v >= v_min (Sec. "Optimization of the
+    MPB"): returns (U_out [n_keep][R], v_out [n_keep], src_of_dst [n_keep])."""
+    if U.dim() != 2 or not U.is_cuda or not U.is_contiguous():
+        raise ValueError("U must be a contiguous device matrix")
+    _dev_tensor(v, "v", torch.float64)
+    N, R = U.shape
+    v_host = np.ascontiguousarray(v.cpu().numpy(), dtype=np.float64)
+    n = _ci(0)
+    _check(_lib.gw_basis_select_count(N, v_host.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(v_min),
+                                      ctypes.byref(n)))
+    U_out = torch.empty((n.value, R), dtype=U.dtype, device=U.device)
+    v_out = torch.empty((n.value,), dtype=torch.float64, device=U.device)
+    src = torch.empty((max(1, n.value),), dtype=torch.int32, device=U.device)
+    _check(_lib.gw_basis_select(_stream(stream), N, R, U.element_size(), U.data_ptr(), v.data_ptr(), float(v_min),
+                                n.value, U_out.data_ptr(), v_out.data_ptr(), src.data_ptr()))
+    return U_out, v_out, src[:n.value]
 

@@ -224,3 +224,18 @@ def test_real_inputs_validation(b):
     assert b.lib().gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(out)) == -1
     d.real_inputs = 1
     assert b.lib().gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 0 and out.value > 0
+
+
+def test_basis_select_count(b):
+    L = b.lib()
+    v = np.array([5.0, 1.0, 3.0, 0.5, 3.0])
+    n = ctypes.c_int(-1)
+    ptr = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.gw_basis_select_count(5, ptr, 3.0, ctypes.byref(n)) == 0 and n.value == 3
+    assert L.gw_basis_select_count(5, ptr, 0.0, ctypes.byref(n)) == 0 and n.value == 5
+    assert L.gw_basis_select_count(5, ptr, 9.0, ctypes.byref(n)) == 0 and n.value == 0
+    assert L.gw_basis_select_count(0, ptr, 1.0, ctypes.byref(n)) == -1
+    assert L.gw_basis_select_count(5, ptr, float("nan"), ctypes.byref(n)) == -1
+    v[2] = np.inf
+    assert L.gw_basis_select_count(5, ptr, 1.0, ctypes.byref(n)) == -1
+    assert L.gw_basis_select(None, 4, 4, 12, 1, 1, 0.0, 1, 1, 1, 1) == -1      # element size
