@@ -162,3 +162,27 @@ def test_split_bf16_kernel_variants(lib, pipeline, pv, staging):
     print(f"pipeline {pipeline} projection variant {pv} staging {staging}: P max rel err {err.max():.2e}, M rel err {merr:.2e}")
     assert err.max() < TOL
     assert merr < 1e-5
+
+
+@pytest.mark.parametrize("real", [False, True])
+@pytest.mark.parametrize("N,R", [(1, 1), (1, 40), (5, 1)])
+def test_extreme_shapes_max_frequencies(lib, real, N, R):
+    """Degenerate sizes (one basis function, one grid point) with the maximum
+    of 64 frequencies on the default split-BF16 pipeline (complex and real)."""
+    import torch
+    shape = dict(n_k=2, n_b=8, R=R, N=N, n_occ=2, n_unocc=5)
+    om = np.concatenate([[0.0], np.geomspace(0.01, 50.0, 63)])
+    inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=17, omega=om)
+    if real:
+        U = np.ascontiguousarray(inp.U.real, dtype=np.float32)
+        psi = np.ascontiguousarray(inp.psi.real, dtype=np.float32)
+        Ud, pd = torch.from_numpy(U).to("cuda"), torch.from_numpy(psi).to("cuda")
+        U64, p64 = U.astype(np.complex128), psi.astype(np.complex128)
+    else:
+        Ud, pd = _dev(inp)
+        U64, p64 = _rounded(inp)
+    P = lib.gw_polarization(Ud, pd, inp.eps, om, 2, precision="split_bf16", kq=inp.kq, real=real)
+    torch.cuda.synchronize()
+    ref = orc.polarization(U64, p64, inp.eps, om, 2, kq=inp.kq)
+    err = orc.rel_fro(P.cpu().numpy(), ref)
+    assert err.max() < TOL, err.max()
