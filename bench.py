@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--mpb", action="store_true",
                     help="basis optimization study instead: Sigma_c and time against the Coulomb-eigenvalue "
                          "threshold v_min on the training-run shapes")
+    ap.add_argument("--tuning", action="append", default=[], metavar="KEY=VALUE",
+                    help="kernel selection switch passed to gw_set_tuning before the run (repeatable)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c5.json"),
                     help="measured per-launch HBM traffic of the dominant kernel (from rocprofv3 --pmc)")
     return ap.parse_args()
@@ -411,6 +413,12 @@ def main() -> int:
         return copy_calibration()
     if a.summarize_pmc:
         return summarize_pmc(a)
+    if a.tuning:
+        from paper_1003_0316_amd import binding as gw
+        for kv in a.tuning:
+            key, _, value = kv.partition("=")
+            gw.gw_set_tuning(key, int(value))
+            log(f"tuning {key} = {int(value)}")
     if a.traffic_driver:
         return traffic_driver(a)
     if a.sigma:
@@ -623,7 +631,8 @@ def main() -> int:
                                f"unocc bands, {n_om} imaginary frequencies, explicit bands to {cutoff}",
                    "precision": a.precision, "surrogate": surrogate is not None,
                    "surrogate_judge": sur_report or None,
-                   "step": "P (projection + accumulation) + surrogate + W (FP64 screening)"},
+                   "step": "P (projection + accumulation) + surrogate + W (FP64 screening)",
+                   **({"tuning": a.tuning} if a.tuning else {})},
         "kernels_s_per_step": breakdown,
         "roofline": roofline,
         "cpu_baseline": cpu,

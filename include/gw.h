@@ -324,7 +324,9 @@ int gw_sigma_c(void* stream, const gw_sigma_desc* d_host, void* ws, size_t ws_by
  *   "gemm_staging"        pipeline 2 only: 1: 4 waves, operand stages pass
  *                         through registers into LDS; 2: 4 waves, direct
  *                         global-to-LDS copies; 3 (default): 8 waves (two per
- *                         SIMD), register staging.
+ *                         SIMD), register staging; 4: 8 waves in ping-pong
+ *                         (the two waves of a SIMD alternate between MFMAs
+ *                         and memory work; same results bit for bit).
  * Values out of range and unknown keys give GW_ERR_INVALID_ARG.  Not
  * thread-safe: set before launching work. */
 int gw_set_tuning(const char* key_host, int value);

@@ -1131,7 +1131,7 @@ extern "C" int gw_set_tuning(const char* key, int value) {
     return GW_OK;
   }
   if (k == "gemm_staging") {
-    if (value < 1 || value > 3) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: gemm_staging is 1, 2 or 3");
+    if (value < 1 || value > 4) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: gemm_staging is 1 to 4");
     gw::g_gemm_staging = value;
     return GW_OK;
   }

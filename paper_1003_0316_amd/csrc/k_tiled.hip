@@ -1000,6 +1000,182 @@ __global__ __launch_bounds__(GT8, 1) void gemm8_bf16x3_kernel(GemmArgs g) {
       }
 }
 
+template <int AW>
+__device__ __forceinline__ void pp_frags(Frags8<AW>& f, const uint32_t* L, int s, int h, int wm, int half, int c0,
+                                         int l32) {
+#pragma unroll
+  for (int q = 0; q < AW; ++q)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+      f.a[q][rb] = *reinterpret_cast<const uint4*>(L + q * WD + lane_off(s * 2 + h, wm * 64 + rb * 32 + l32));
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+      f.b[q][cb] =
+          *reinterpret_cast<const uint4*>(L + (AW + 2 * half + q) * WD + lane_off(s * 2 + h, c0 + cb * 32 + l32));
+}
+
+// Workgroup barrier that no instruction is scheduled across (MFMAs included),
+// so that each phase holds exactly its own work.
+__device__ __forceinline__ void pp_barrier() {
+  __builtin_amdgcn_sched_barrier(0);
+  lds_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void pp_mma(const Frags8<4>& f, floatx16 (&cr)[2][2], floatx16 (&ci)[2][2]) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      cr[rb][cb] = mma(f.a[0][rb], f.b[0][cb], cr[rb][cb]);
+      ci[rb][cb] = mma(f.a[2][rb], f.b[0][cb], ci[rb][cb]);
+      cr[rb][cb] = mma(f.a[0][rb], f.b[1][cb], cr[rb][cb]);
+      ci[rb][cb] = mma(f.a[2][rb], f.b[1][cb], ci[rb][cb]);
+      cr[rb][cb] = mma(f.a[1][rb], f.b[0][cb], cr[rb][cb]);
+      ci[rb][cb] = mma(f.a[3][rb], f.b[0][cb], ci[rb][cb]);
+    }
+}
+
+// ------------------------------------------- 8-wave ping-pong variant
+// Same tile, operands and epilogues as gemm8_bf16x3_kernel; the two waves on
+// each SIMD (group 0: waves 0-3, rows 0-63; group 1: waves 4-7, rows 64-127)
+// alternate: while one group issues the MFMAs of a step from fragments it
+// already holds, the other reads its next fragments from LDS and does the
+// staging (its half of the next stage's LDS stores and global loads), and a
+// workgroup barrier separates the phases.  Group 1 runs one phase behind.
+template <int OUT>
+__global__ __launch_bounds__(GT8, 1) void gemm8pp_bf16x3_kernel(GemmArgs g) {
+  constexpr int AW = 4;
+  constexpr int STAGE = (AW + 4) * WD;
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  int ti, tj, jw;
+  decode_tile<OUT>(g, ti, tj, jw);
+  const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
+  const uint32_t* B0 = g.B + jw * g.omega_stride + (size_t)(2 * tj) * g.b_bstride;
+  const uint32_t* B1 = B0 + g.b_bstride;
+  const size_t b_step = (size_t)g.b_words * WD;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w >> 2, wn = w & 3;
+  const int grp = wm;                              // wave-uniform
+  const int half = wn >> 1, c0 = (wn & 1) * 64;
+  const int l32 = lane & 31, h = lane >> 5;
+
+  floatx16 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        cr[a][b][v] = 0.f;
+        ci[a][b][v] = 0.f;
+      }
+
+  Staged8<AW> r;
+  stage_load8<AW>(r, Ap, B0, B1, b_step, 0, tid);
+  stage_store8<AW>(r, lds, 0, tid);
+  stage_store8<AW>(r, lds, 1, tid);
+  stage_load8<AW>(r, Ap, B0, B1, b_step, min(1, g.nst - 1), tid);
+  lds_barrier();
+
+  Frags8<AW> f;
+  // Phases are separated by workgroup barriers; group 0 runs
+  //   [fragments s=0 + staging] [MFMA] [fragments s=1] [MFMA]   per stage,
+  // group 1 the same sequence one phase later (one extra barrier in front for
+  // group 1, at the end for group 0), so every phase pairs one group's memory
+  // work with the other's MFMAs.  Buffer (st+1)%2 is written in the phases
+  // 4st and 4st+1 and read from 4st+4 on; its previous contents were last read
+  // in phase 4st-1.
+  if (grp == 1) pp_barrier();
+  for (int st = 0; st < g.nst; ++st) {
+    const uint32_t* L = lds + (st & 1) * STAGE;
+    uint32_t* Ln = lds + ((st + 1) & 1) * STAGE;
+    pp_frags<AW>(f, L, 0, h, wm, half, c0, l32);
+    stage_store8<AW>(r, Ln, 0, tid);
+    stage_store8<AW>(r, Ln, 1, tid);
+    stage_load8<AW>(r, Ap, B0, B1, b_step, min(st + 2, g.nst - 1), tid);
+    pp_barrier();
+    pp_mma(f, cr, ci);
+    pp_barrier();
+    pp_frags<AW>(f, L, 1, h, wm, half, c0, l32);
+    pp_barrier();
+    pp_mma(f, cr, ci);
+    pp_barrier();
+  }
+  if (grp == 0) pp_barrier();
+
+  if constexpr (OUT == OUT_HERK) {
+    float2* E = reinterpret_cast<float2*>(lds);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (half == c) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+              E[row * 128 + c0 + cb * 32 + l32] = make_float2(cr[rb][cb][v], ci[rb][cb][v]);
+            }
+      }
+      __syncthreads();
+      double2* Pj = g.P + (size_t)jw * g.N * g.N;
+#pragma unroll 4
+      for (int e = tid; e < 128 * 128; e += GT8) {
+        const int gi = ti * TM + (e >> 7), gj = tj * TN + c * 128 + (e & 127);
+        if (gi < g.N && gj <= gi) {
+          const float2 x = E[e];
+          double2* pp = Pj + (size_t)gi * g.N + gj;
+          double2 y = *pp;
+          y.x -= (double)x.x;
+          y.y -= (double)x.y;
+          *pp = y;
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * 64 + cb * 32 + l32;
+        const float re = cr[rb][cb][v], im = ci[rb][cb][v];
+        if constexpr (OUT == OUT_TILED) {
+          const int t = tj * TN + col;
+          const size_t bs = (size_t)ti * g.nst_out + t / TK;
+          const int kk = t % TK;
+          g.M[(bs * 4 + (kk >> 2)) * TR * 4 + row * 4 + (kk & 3)] = make_float2(re, im);
+        } else {
+          const int gi = ti * TM + row, gt = tj * TN + col;
+          if (gi < g.N && gt < g.T) g.M[(size_t)gi * g.ldm + gt] = make_float2(re, im);
+        }
+      }
+}
+
+template <int OUT>
+int launch_gemm8pp(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
+  static int attr = 0;
+  constexpr size_t lds_bytes = gemm8_lds_bytes<false>();
+  if (!attr) {
+    GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm8pp_bf16x3_kernel<OUT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    attr = 1;
+  }
+  ProfScope prof(s, name);
+  hipLaunchKernelGGL((gemm8pp_bf16x3_kernel<OUT>), dim3(grid), dim3(GT8), lds_bytes, s, a);
+  GW_LAUNCHED("gemm8pp_bf16x3_kernel");
+  return GW_OK;
+}
+
 template <int OUT, int DMA>
 int enable_gemm_lds() {
   static int done = 0;
@@ -1085,6 +1261,7 @@ int launch_gemm8(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
 
 template <int OUT>
 int launch_gemm(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
+  if (g_gemm_staging == 4) return launch_gemm8pp<OUT>(s, a, grid, name);
   if (g_gemm_staging == 3) return launch_gemm8<OUT>(s, a, grid, name);
   return g_gemm_staging == 2 ? launch_gemm_as<OUT, 1>(s, a, grid, name) : launch_gemm_as<OUT, 0>(s, a, grid, name);
 }

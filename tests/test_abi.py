@@ -150,7 +150,7 @@ def test_tuning_switches_validate(b):
     """gw_set_tuning accepts the documented keys and values only (host-side)."""
     L = b.lib()
     for key, lo, hi, default in (("bf16_pipeline", 1, 2, 2), ("projection_variant", 1, 2, 2),
-                                 ("gemm_staging", 1, 3, 3)):
+                                 ("gemm_staging", 1, 4, 3)):
         for v in (lo, hi):
             assert L.gw_set_tuning(key.encode(), v) == 0
         for v in (lo - 1, hi + 1):

@@ -132,13 +132,14 @@ def test_poisoned_workspace(lib, prec):
     assert torch.equal(P1, P2)
 
 
-@pytest.mark.parametrize("pipeline,pv,staging", [(1, 1, 1), (1, 2, 1), (2, 2, 1), (2, 2, 2), (2, 2, 3)])
+@pytest.mark.parametrize("pipeline,pv,staging", [(1, 1, 1), (1, 2, 1), (2, 2, 1), (2, 2, 2), (2, 2, 3), (2, 2, 4)])
 def test_split_bf16_kernel_variants(lib, pipeline, pv, staging):
     """Every kernel variant of the split-BF16 path meets the same bar (N spans
     two 256-row tiles with a ragged tail; R and the pair count are ragged):
     operands staged inside the GEMM kernels with either projection tiling, and
     pre-tiled operands on the shared GEMM core (4 waves staged through
-    registers or copied straight into LDS, or 8 waves)."""
+    registers or copied straight into LDS, or 8 waves in lockstep or in
+    ping-pong)."""
     import torch
     shape = dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150)
     inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=9, omega=gwsynth.omega_mesh("m16"))
