@@ -69,6 +69,11 @@ def parse():
     ap.add_argument("--mpb", action="store_true",
                     help="basis optimization study instead: Sigma_c and time against the Coulomb-eigenvalue "
                          "threshold v_min on the training-run shapes")
+    ap.add_argument("--surrogate-ablation", action="store_true",
+                    help="ablation of the high-band correction on held-out training-run seeds: truncation, "
+                         "missing diagonal only, congruence (learned and exact), and a rank-8 term in the "
+                         "leading eigenvectors of -P_ret with coefficients fitted to the true residual")
+    ap.add_argument("--ablation-seeds", type=int, default=4, help="held-out seeds for --surrogate-ablation")
     ap.add_argument("--tuning", action="append", default=[], metavar="KEY=VALUE",
                     help="kernel selection switch passed to gw_set_tuning before the run (repeatable)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c5.json"),
@@ -120,6 +125,91 @@ def traffic_driver(a) -> int:
     call.run()
     torch.cuda.synchronize()
     print(json.dumps({"traffic_driver": a.workload, "pairs": shp.n_occ * cutoff, "precision": a.precision}))
+    return 0
+
+
+def surrogate_ablation(a) -> int:
+    """Which part of the proposed correction carries the gain (training-run
+    shapes: N=1000, R=8192, 64 + 1500 bands, 4 k-sets, 16 frequencies; the
+    shipped model; held-out seeds; cutoffs 300 and 375).  Relative Frobenius
+    error against the full-band P, per frequency, for
+      truncation           P_ret
+      diag_learned         P_ret - diag(d_hat)            d_hat = |P_ret,II| e^y
+      diag_exact           P_ret - diag(d)                d the true missing diagonal
+      congruence_learned   P_ret + D P_ret D              (the shipped surrogate, library kernels)
+      congruence_exact     the same with D from d
+      rank8_fitted         congruence_learned - X diag(c) X^H, X the 8 leading
+                           eigenvectors of -P_ret, c >= 0 fitted to the true
+                           residual (the best any learned rank-8 term of this form
+                           can do)
+      best_rank8           congruence_learned + the best rank-8 approximation of
+                           the residual itself (the best any rank-8 term can do)
+    The GPU computes P (split BF16) and the learned correction; the analysis
+    (eigenvectors, fits) is FP64 NumPy on the host.  One JSON line."""
+    import numpy as np
+    import torch
+
+    import gwsynth
+    from paper_1003_0316_amd import binding as gw
+    from paper_1003_0316_amd.surrogate import Surrogate
+    from paper_1003_0316_amd.train_surrogate import SEED0, run_partials
+    dev = torch.device("cuda:0")
+    sur = Surrogate.load_default(dev)
+    shp = gwsynth.SHAPES["c4train"]
+    cuts = (300, 375)
+    names = ["truncation", "diag_learned", "diag_exact", "congruence_learned", "congruence_exact", "rank8_fitted",
+             "best_rank8"]
+    errs = {c: {v: [] for v in names} for c in cuts}
+    seeds = [gwsynth.BASE_SEED + SEED0 + 200 + i for i in range(a.ablation_seeds)]
+    for s in seeds:
+        inp, eps_dev, parts, P_full = run_partials(s, dev, cuts=cuts)
+        Pf_all = P_full.cpu().numpy()
+        n_om, N = Pf_all.shape[0], Pf_all.shape[1]
+        for c in cuts:
+            Pr_t = parts[c]
+            Y, _ = sur.predict(Pr_t, eps_dev, inp.omega, shp.n_occ, c, inp.kq)
+            y = Y[:, 0].double().clamp(-30.0, 30.0).cpu().numpy().reshape(n_om, N)
+            Pc_t = Pr_t.clone()
+            gw.gw_surrogate_apply(Pc_t, Y, sur.mlp.n_out)
+            Pr_all, Pc_all = Pr_t.cpu().numpy(), Pc_t.cpu().numpy()
+            rows = {v: [] for v in names}
+            for j in range(n_om):
+                pr, pf, pc = Pr_all[j], Pf_all[j], Pc_all[j]
+                nf = np.linalg.norm(pf)
+                err = lambda X: float(np.linalg.norm(X - pf) / nf)
+                dr = np.real(np.diag(pr))
+                d = dr - np.real(np.diag(pf))
+                d_hat = np.abs(dr) * np.exp(y[j])
+                Dx = np.sqrt(np.maximum(d, 0.0) / np.abs(dr))
+                rows["truncation"].append(err(pr))
+                rows["diag_learned"].append(err(pr - np.diag(d_hat)))
+                rows["diag_exact"].append(err(pr - np.diag(d)))
+                rows["congruence_learned"].append(err(pc))
+                rows["congruence_exact"].append(err(pr + Dx[:, None] * pr * Dx[None, :]))
+                Rs = pf - pc
+                _, V = np.linalg.eigh(-pr)
+                X = V[:, -8:]
+                cf = np.maximum(-np.real(np.einsum("ia,ij,ja->a", X.conj(), Rs, X)), 0.0)
+                rows["rank8_fitted"].append(err(pc - (X * cf) @ X.conj().T))
+                er, Vr = np.linalg.eigh(Rs)
+                idx = np.argsort(-np.abs(er))[:8]
+                rows["best_rank8"].append(err(pc + (Vr[:, idx] * er[idx]) @ Vr[:, idx].conj().T))
+            for v in names:
+                errs[c][v].append(rows[v])
+        log(f"seed {s}: cut 300 congruence {np.mean(errs[300]['congruence_learned'][-1]):.4f}, "
+            f"rank8_fitted {np.mean(errs[300]['rank8_fitted'][-1]):.4f}, best_rank8 "
+            f"{np.mean(errs[300]['best_rank8'][-1]):.4f}")
+        del parts, P_full
+        torch.cuda.empty_cache()
+    out = {}
+    for c in cuts:
+        out[str(c)] = {v: {"mean": round(float(np.mean(e)), 5), "max": round(float(np.max(e)), 5),
+                           "per_omega_mean": [round(float(x), 5) for x in np.mean(e, axis=0)]}
+                       for v, e in errs[c].items()}
+    print(json.dumps({"surrogate_ablation": out, "seeds": seeds,
+                      "config": {"workload": "N_k=4, N=1000, R=8192, 64 occ + 1500 unocc bands, 16 imaginary "
+                                             "frequencies (training-run shapes), held-out seeds",
+                                 "precision": "split_bf16"}}))
     return 0
 
 
@@ -427,6 +517,8 @@ def main() -> int:
         return real_bench(a)
     if a.mpb:
         return mpb_bench(a)
+    if a.surrogate_ablation:
+        return surrogate_ablation(a)
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build runs on one GPU only "
               f"(the k-point / occupied-band shards and the reduce-scatter of P over frequencies are "
