@@ -86,7 +86,7 @@ def test_polarization_deterministic(lib):
     assert torch.equal(P1, P2)
 
 
-@pytest.mark.parametrize("N", [120, 1, 33, 200])
+@pytest.mark.parametrize("N", [120, 1, 33, 130, 200, 257])
 def test_screen_fp64(lib, N):
     import torch
     shp = gwsynth.make_shape(n_k=2, n_b=60, R=256, N=N, n_occ=3, n_unocc=20)
