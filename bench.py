@@ -627,6 +627,10 @@ def main() -> int:
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[peak_dtype], 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4), "alg_flops_per_launch": alg_per_launch,
                 "launches": dk["launches"]}
+    if pre in ("bf16", "f16") and dom != "update_kernel":
+        # a split product executes three 16-bit MFMA products per algorithmic one
+        roofline["executed_tflops"] = round(3.0 * achieved, 2)
+        roofline["executed_frac"] = round(3.0 * achieved / PEAK_TFLOPS[peak_dtype], 4)
     breakdown = {k: round(v["total_ms"] / a.steps / 1e3, 4) for k, v in kernels.items()}
     log(f"kernels (s/step): {breakdown}; dominant {dom} at {achieved:.1f} TFLOP/s")
 
