@@ -130,34 +130,42 @@ __global__ void spline_basis_kernel(Mesh mesh, double* __restrict__ C) {
 // folded kernel times dw'/dlambda is -i/(lambda + c1) + i/(lambda + c2) with
 // a = i w - e, c1 = a / (i - a), c2 = a / (-i - a); the tail gives
 // w_L^2 (2/a) [1/w_L - (1/a)((pi/2) sgn(-e) - atan(w_L / a))].
-__global__ void sigma_weights_kernel(Mesh mesh, Mesh out, int nb, const double* __restrict__ eps, double mu,
-                                     const double* __restrict__ C, double2* __restrict__ wts) {
-  const long gid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+// One wavefront per (band b, output frequency o): its lanes first form the
+// interval integrals J[i][p] = -i F_p(lambda_i + c1) + i F_p(lambda_i + c2)
+// (shared by every mesh point j) in LDS, then lane j contracts them with the
+// spline coefficients C[i][p][j].
+__global__ __launch_bounds__(256) void sigma_weights_kernel(Mesh mesh, Mesh out, int nb,
+                                                            const double* __restrict__ eps, double mu,
+                                                            const double* __restrict__ C, double2* __restrict__ wts) {
+  __shared__ cd Js[4][(kMaxMesh - 1) * 4];
+  const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long item = blockIdx.x * 4L + g;
+  const bool live = item < (long)nb * out.n;
   const int n = mesh.n, ni = n - 1;
-  const long total = (long)nb * out.n * n;
-  if (gid >= total) return;
-  const int j = (int)(gid % n);
-  const int o = (int)((gid / n) % out.n);
-  const int b = (int)(gid / ((long)n * out.n));
-  const double e = eps[b] - mu;
+  const int o = live ? (int)(item % out.n) : 0;
+  const int b = live ? (int)(item / out.n) : 0;
+  const double e = live ? eps[b] - mu : 1.0;
   const double w = out.w[o];
   const cd a = mk(-e, w);
   const cd c1 = dvd(a, sub(mk(0.0, 1.0), a));
   const cd c2 = dvd(a, sub(mk(0.0, -1.0), a));
-  cd acc = mk(0.0, 0.0);
-  double l0 = mesh.w[0] / (1.0 + mesh.w[0]);
-  for (int i = 0; i < ni; ++i) {
+  for (int q = lane; q < ni * 4; q += 64) {
+    const int i = q >> 2, p = q & 3;
+    const double l0 = mesh.w[i] / (1.0 + mesh.w[i]);
     const double l1 = mesh.w[i + 1] / (1.0 + mesh.w[i + 1]);
     const double h = l1 - l0;
-    const cd d1 = add(mk(l0, 0.0), c1), d2 = add(mk(l0, 0.0), c2);
-    for (int p = 0; p < 4; ++p) {
-      const double coef = C[((size_t)i * 4 + p) * n + j];
-      if (coef == 0.0) continue;
-      const cd f1 = int_pow_over_lin(p, d1, h), f2 = int_pow_over_lin(p, d2, h);
-      const cd df = sub(f2, f1);
-      acc = add(acc, scl(mk(-df.y, df.x), coef));               // coef * (-i f1 + i f2)
-    }
-    l0 = l1;
+    const cd f1 = int_pow_over_lin(p, add(mk(l0, 0.0), c1), h);
+    const cd f2 = int_pow_over_lin(p, add(mk(l0, 0.0), c2), h);
+    const cd df = sub(f2, f1);
+    Js[g][q] = mk(-df.y, df.x);                                  // -i f1 + i f2
+  }
+  __syncthreads();
+  if (!live || lane >= n) return;
+  const int j = lane;
+  cd acc = mk(0.0, 0.0);
+  for (int q = 0; q < ni * 4; ++q) {
+    const double coef = C[(size_t)q * n + j];
+    if (coef != 0.0) acc = add(acc, scl(Js[g][q], coef));
   }
   if (j == n - 1) {
     const double wl = mesh.w[n - 1];
@@ -167,7 +175,7 @@ __global__ void sigma_weights_kernel(Mesh mesh, Mesh out, int nb, const double* 
     const cd inner = sub(mk(1.0 / wl, 0.0), mul(inv_a, sub(mk(0.5 * M_PI * sg, 0.0), at)));
     acc = add(acc, scl(mul(inv_a, inner), 2.0 * wl * wl));
   }
-  wts[gid] = make_double2(acc.x, acc.y);
+  wts[item * n + j] = make_double2(acc.x, acc.y);
 }
 
 // Y = (W - diag v) M: complex FP64, 64 x 64 output tiles, 256 threads with
@@ -396,10 +404,11 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
                      d.n_states * d.n_out);
   GW_LAUNCHED("zero_c128_kernel");
   const long nw = (long)nb * d.n_out * d.n_mesh;
+  const long nbo = (long)nb * d.n_out;
   // the weights depend on the band set only: once per set
   for (int k = 0; k < d.n_k; ++k) {
     ProfScope prof(s, "sigma_weights_kernel");
-    hipLaunchKernelGGL(sigma_weights_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, mesh, out, nb,
+    hipLaunchKernelGGL(sigma_weights_kernel, dim3((unsigned)((nbo + 3) / 4)), dim3(256), 0, s, mesh, out, nb,
                        d.eps + (size_t)k * nb, d.mu, C, wts + (size_t)k * nw);
     GW_LAUNCHED("sigma_weights_kernel");
   }
