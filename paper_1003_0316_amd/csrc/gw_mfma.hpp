@@ -31,10 +31,14 @@ size_t tiled_pol_workspace_real(int N, int R, int tc, int n_omega);
 int tiled_polarization_real(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
                             const OmegaList& om, void* ws);
 
-// Correlation self-energy, split-BF16 quadratic forms (k_tiled.hip).
-size_t tiled_sigma_workspace(int N, int R, int nb);
-int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const float2* U, bool tile_u,
-                          const float2* psi_state, const float2* psi_all, const double2* W, const double* v,
-                          double* q, void* ws);
+// Correlation self-energy, split-BF16 quadratic forms (k_tiled.hip) for a
+// batch of g states sharing one momentum transfer: q [n_mesh][cols], the
+// states' columns side by side, cols = tiled_sigma_cols(nb, g), state i at
+// column i * cols / g.
+int tiled_sigma_cols(int nb, int g);
+size_t tiled_sigma_workspace(int N, int R, int nb, int g);
+int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int g, int n_mesh, const float2* U, bool tile_u,
+                          const float2* const* psi_state, const float2* const* psi_all, const double2* W,
+                          const double* v, double* q, void* ws);
 
 }  // namespace gw

@@ -274,14 +274,15 @@ __global__ void coldot_sum_kernel(int nb, int chunks, const double* __restrict__
 // frequency, fixed-order reduction.
 __global__ __launch_bounds__(256) void sigma_contract_kernel(int nb, int n_mesh, int n_out,
                                                              const double2* __restrict__ wts,
-                                                             const double* __restrict__ q, double2* __restrict__ sig) {
+                                                             const double* __restrict__ q, long ldq,
+                                                             double2* __restrict__ sig) {
   __shared__ double rx[256], ry[256];
   const int o = blockIdx.x;
   double ax = 0.0, ay = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) {
     const double2* w = wts + ((size_t)b * n_out + o) * n_mesh;
     for (int j = 0; j < n_mesh; ++j) {
-      const double qq = q[(size_t)j * nb + b];
+      const double qq = q[(size_t)j * ldq + b];
       ax = fma(w[j].x, qq, ax);
       ay = fma(w[j].y, qq, ay);
     }
@@ -345,22 +346,34 @@ int validate_sigma(const gw_sigma_desc* dp) {
   return GW_OK;
 }
 
+// States per batch of the split path (they share the W^c operand words of a
+// transfer and one wide GEMM per mesh point).
+constexpr int kSigmaBatch = 16;
+
 struct SigmaWs {
   size_t total = 0;
   size_t quad = 0;   // split path: tiled operands
+  int batch = 1;     // split path: states per batch
+  long ldq = 0;      // columns of q
 };
 
 SigmaWs sigma_ws(const gw_sigma_desc& d) {
   SigmaWs w;
   const int ni = d.n_mesh - 1;
+  if (d.precision == GW_FP64) {
+    w.ldq = d.n_bands;
+  } else {
+    w.batch = std::min(d.n_states, kSigmaBatch);
+    w.ldq = tiled_sigma_cols(d.n_bands, w.batch);
+  }
   size_t t = align_up((size_t)ni * 4 * d.n_mesh * sizeof(double)) +
              align_up((size_t)d.n_k * d.n_bands * d.n_out * d.n_mesh * sizeof(double2)) +
-             align_up((size_t)d.n_mesh * d.n_bands * sizeof(double));
+             align_up((size_t)d.n_mesh * w.ldq * sizeof(double));
   if (d.precision == GW_FP64) {
     t += 2 * align_up((size_t)d.N * d.n_bands * sizeof(double2)) +
          align_up((size_t)CD_CHUNKS64 * d.n_bands * sizeof(double));
   } else {
-    w.quad = tiled_sigma_workspace(d.N, d.R, d.n_bands);
+    w.quad = tiled_sigma_workspace(d.N, d.R, d.n_bands, w.batch);
     t += align_up(w.quad);
   }
   w.total = t;
@@ -396,7 +409,7 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
   Carver cv(ws);
   double* C = cv.take<double>((size_t)ni * 4 * d.n_mesh);
   double2* wts = cv.take<double2>((size_t)d.n_k * nb * d.n_out * d.n_mesh);   // per band set
-  double* q = cv.take<double>((size_t)d.n_mesh * nb);
+  double* q = cv.take<double>((size_t)d.n_mesh * need.ldq);
   double2* sig = static_cast<double2*>(d.sigma);
   hipLaunchKernelGGL(spline_basis_kernel, dim3(1), dim3(kMaxMesh), 0, s, mesh, C);
   GW_LAUNCHED("spline_basis_kernel");
@@ -424,12 +437,12 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
   } else {
     quad_ws = cv.take<char>(need.quad);
   }
-  for (int si = 0; si < d.n_states; ++si) {
-    const int s0 = d.state_set_host[si], n0 = d.state_band_host[si];
-    for (int t = 0; t < d.n_k; ++t) {
-      const int s2 = (s0 + t) % d.n_k;
-      const double2* W = static_cast<const double2*>(d.W_host[t]);
-      if (d.precision == GW_FP64) {
+  if (d.precision == GW_FP64) {
+    for (int si = 0; si < d.n_states; ++si) {
+      const int s0 = d.state_set_host[si], n0 = d.state_band_host[si];
+      for (int t = 0; t < d.n_k; ++t) {
+        const int s2 = (s0 + t) % d.n_k;
+        const double2* W = static_cast<const double2*>(d.W_host[t]);
         const double2* psi = static_cast<const double2*>(d.psi);
         const double2* pstate = psi + ((size_t)s0 * nb + n0) * d.R;
         const double2* pall = psi + (size_t)s2 * nb * d.R;
@@ -451,18 +464,37 @@ extern "C" int gw_sigma_c(void* stream, const gw_sigma_desc* dp, void* ws, size_
                              q + (size_t)j * nb);
           GW_LAUNCHED("coldot_sum_kernel");
         }
-      } else {
-        const float2* psi = static_cast<const float2*>(d.psi);
-        const float2* pstate = psi + ((size_t)s0 * nb + n0) * d.R;
-        const float2* pall = psi + (size_t)s2 * nb * d.R;
-        if ((st = tiled_sigma_quadforms(s, d.N, d.R, nb, d.n_mesh, static_cast<const float2*>(d.U), !u_tiled, pstate,
-                                        pall, W, d.v, q, quad_ws)) != GW_OK)
-          return st;
-        u_tiled = true;
+        hipLaunchKernelGGL(sigma_contract_kernel, dim3(d.n_out), dim3(256), 0, s, nb, d.n_mesh, d.n_out,
+                           wts + (size_t)s2 * nw, q, (long)nb, sig + (size_t)si * d.n_out);
+        GW_LAUNCHED("sigma_contract_kernel");
       }
-      hipLaunchKernelGGL(sigma_contract_kernel, dim3(d.n_out), dim3(256), 0, s, nb, d.n_mesh, d.n_out,
-                         wts + (size_t)s2 * nw, q, sig + (size_t)si * d.n_out);
-      GW_LAUNCHED("sigma_contract_kernel");
+    }
+    return GW_OK;
+  }
+  // split BF16: batches of states share each transfer's W^c words and GEMMs
+  const float2* psi = static_cast<const float2*>(d.psi);
+  std::vector<const float2*> pst(need.batch), pal(need.batch);
+  for (int b0 = 0; b0 < d.n_states; b0 += need.batch) {
+    const int g = std::min(need.batch, d.n_states - b0);
+    const long ldq = tiled_sigma_cols(nb, g);
+    const long col = ldq / g;
+    for (int t = 0; t < d.n_k; ++t) {
+      const double2* W = static_cast<const double2*>(d.W_host[t]);
+      for (int i = 0; i < g; ++i) {
+        const int s0 = d.state_set_host[b0 + i], n0 = d.state_band_host[b0 + i];
+        pst[i] = psi + ((size_t)s0 * nb + n0) * d.R;
+        pal[i] = psi + (size_t)((s0 + t) % d.n_k) * nb * d.R;
+      }
+      if ((st = tiled_sigma_quadforms(s, d.N, d.R, nb, g, d.n_mesh, static_cast<const float2*>(d.U), !u_tiled,
+                                      pst.data(), pal.data(), W, d.v, q, quad_ws)) != GW_OK)
+        return st;
+      u_tiled = true;
+      for (int i = 0; i < g; ++i) {
+        const int s2 = (d.state_set_host[b0 + i] + t) % d.n_k;
+        hipLaunchKernelGGL(sigma_contract_kernel, dim3(d.n_out), dim3(256), 0, s, nb, d.n_mesh, d.n_out,
+                           wts + (size_t)s2 * nw, q + i * col, ldq, sig + (size_t)(b0 + i) * d.n_out);
+        GW_LAUNCHED("sigma_contract_kernel");
+      }
     }
   }
   return GW_OK;

@@ -1480,21 +1480,25 @@ int tiled_polarization_real(hipStream_t s, const gw_pol_desc& d, const std::vect
 // and one transfer, split BF16 on the GEMM core: the projections m of the
 // products conj(psi_state) psi_n' (all bands n'), then Y_j = W^c_j M and the
 // column dots.
+// Batched quadratic forms of the self-energy: the states of a batch share
+// W^c(t), so their projections sit side by side as the columns of one operand,
+// each state's bands padded to whole 256-column tiles.
 struct SigmaDims {
-  int nI, nstR, nstN, nbp, nTb;
+  int nI, nstR, nstN, nbp, cols, nTb;
   size_t u_words, q_words, m_c64, mt_words, w_words, part;
-  SigmaDims(int N, int R, int nb) {
+  SigmaDims(int N, int R, int nb, int g) {
     nI = cdiv(N, TR);
     nstR = cdiv(R, TK);
     nstN = cdiv(N, TK);
     nbp = cdiv(nb, TN) * TN;
-    nTb = nbp / TR;
+    cols = g * nbp;
+    nTb = cols / TR;
     u_words = (size_t)nI * nstR * 4 * WD;
-    q_words = (size_t)nTb * nstR * 2 * WD;
-    m_c64 = (size_t)N * nbp;
+    q_words = (size_t)(nbp / TR) * nstR * 2 * WD;   // pair products of one state
+    m_c64 = (size_t)N * cols;
     mt_words = (size_t)nTb * nstN * 2 * WD;
     w_words = (size_t)nI * nstN * 4 * WD;
-    part = (size_t)CD_CHUNKS * nb;
+    part = (size_t)CD_CHUNKS * cols;
   }
   size_t bytes() const {
     return align_up(u_words * 4) + align_up(q_words * 4) + 2 * align_up(m_c64 * 8) + align_up(mt_words * 4) +
@@ -1502,12 +1506,20 @@ struct SigmaDims {
   }
 };
 
-size_t tiled_sigma_workspace(int N, int R, int nb) { return SigmaDims(N, R, nb).bytes(); }
+namespace {
+__global__ void zero_u32_kernel(uint32_t* __restrict__ p, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) p[e] = 0u;
+}
+}  // namespace
 
-int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const float2* U, bool tile_u,
-                          const float2* psi_state, const float2* psi_all, const double2* W, const double* v,
-                          double* q, void* ws) {
-  SigmaDims d(N, R, nb);
+int tiled_sigma_cols(int nb, int g) { return g * (cdiv(nb, TN) * TN); }
+
+size_t tiled_sigma_workspace(int N, int R, int nb, int g) { return SigmaDims(N, R, nb, g).bytes(); }
+
+int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int g, int n_mesh, const float2* U, bool tile_u,
+                          const float2* const* psi_state, const float2* const* psi_all, const double2* W,
+                          const double* v, double* q, void* ws) {
+  SigmaDims d(N, R, nb, g);
   Carver cv(ws);
   uint32_t* Uw = cv.take<uint32_t>(d.u_words);
   uint32_t* Q = cv.take<uint32_t>(d.q_words);
@@ -1520,23 +1532,29 @@ int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const
   int st;
   TiledDims td(N, R, nb, 0);
   if (tile_u && (st = launch_tile_u(s, td, N, R, U, Uw)) != GW_OK) return st;
-  if ((st = launch_pair_product(s, td, R, psi_state, psi_all, nb, 0, nb, Q)) != GW_OK) return st;
-  GemmArgs a{};
-  a.A = Uw;
-  a.B = Q;
-  a.b_words = 2;
-  a.nst = d.nstR;
-  a.a_bstride = (size_t)d.nstR * 4 * WD;
-  a.b_bstride = (size_t)d.nstR * 2 * WD;
-  a.nI = d.nI;
-  a.nTj = d.nbp / TN;
-  a.N = N;
-  a.T = nb;
-  a.M = M;
-  a.ldm = d.nbp;
-  if ((st = launch_gemm<OUT_ROWS>(s, a, d.nI * a.nTj, "sigma_project_kernel")) != GW_OK) return st;
-  hipLaunchKernelGGL(tile_cols_kernel, dim3(stream_blocks((size_t)d.nTb * d.nstN * 4 * TR)), dim3(256), 0, s, N, nb,
-                     d.nTb, d.nstN, M, (long)d.nbp, Mt);
+  // the padding columns of every state's block stay zero
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(stream_blocks(d.m_c64 * 2)), dim3(256), 0, s,
+                     reinterpret_cast<uint32_t*>(M), d.m_c64 * 2);
+  GW_LAUNCHED("zero_u32_kernel");
+  for (int i = 0; i < g; ++i) {
+    if ((st = launch_pair_product(s, td, R, psi_state[i], psi_all[i], nb, 0, nb, Q)) != GW_OK) return st;
+    GemmArgs a{};
+    a.A = Uw;
+    a.B = Q;
+    a.b_words = 2;
+    a.nst = d.nstR;
+    a.a_bstride = (size_t)d.nstR * 4 * WD;
+    a.b_bstride = (size_t)d.nstR * 2 * WD;
+    a.nI = d.nI;
+    a.nTj = d.nbp / TN;
+    a.N = N;
+    a.T = nb;
+    a.M = M + (size_t)i * d.nbp;
+    a.ldm = d.cols;
+    if ((st = launch_gemm<OUT_ROWS>(s, a, d.nI * a.nTj, "sigma_project_kernel")) != GW_OK) return st;
+  }
+  hipLaunchKernelGGL(tile_cols_kernel, dim3(stream_blocks((size_t)d.nTb * d.nstN * 4 * TR)), dim3(256), 0, s, N,
+                     d.cols, d.nTb, d.nstN, M, (long)d.cols, Mt);
   GW_LAUNCHED("tile_cols_kernel");
   for (int j = 0; j < n_mesh; ++j) {
     hipLaunchKernelGGL(tile_wc_kernel, dim3(stream_blocks((size_t)d.nI * d.nstN * 4 * TR)), dim3(256), 0, s, N, d.nI,
@@ -1550,17 +1568,17 @@ int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int n_mesh, const
     b.a_bstride = (size_t)d.nstN * 4 * WD;
     b.b_bstride = (size_t)d.nstN * 2 * WD;
     b.nI = d.nI;
-    b.nTj = d.nbp / TN;
+    b.nTj = d.cols / TN;
     b.N = N;
-    b.T = nb;
+    b.T = d.cols;
     b.M = Y;
-    b.ldm = d.nbp;
+    b.ldm = d.cols;
     if ((st = launch_gemm<OUT_ROWS>(s, b, d.nI * b.nTj, "sigma_wm_kernel")) != GW_OK) return st;
-    hipLaunchKernelGGL(coldot_f32_kernel, dim3(cdiv(nb, 32), CD_CHUNKS), dim3(256), 0, s, N, nb, M, Y, (long)d.nbp,
-                       rows_per_chunk, part);
+    hipLaunchKernelGGL(coldot_f32_kernel, dim3(cdiv(d.cols, 32), CD_CHUNKS), dim3(256), 0, s, N, d.cols, M, Y,
+                       (long)d.cols, rows_per_chunk, part);
     GW_LAUNCHED("coldot_f32_kernel");
-    hipLaunchKernelGGL(coldot_reduce_kernel, dim3(cdiv(nb, 256)), dim3(256), 0, s, nb, CD_CHUNKS, part,
-                       q + (size_t)j * nb);
+    hipLaunchKernelGGL(coldot_reduce_kernel, dim3(cdiv(d.cols, 256)), dim3(256), 0, s, d.cols, CD_CHUNKS, part,
+                       q + (size_t)j * d.cols);
     GW_LAUNCHED("coldot_reduce_kernel");
   }
   return GW_OK;

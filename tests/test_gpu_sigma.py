@@ -109,3 +109,33 @@ def test_sigma_deterministic_and_workspace_reuse(lib):
     b = call.run(ws).clone()
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_sigma_split_bf16_batches(lib):
+    """18 states: a full batch of 16 sharing each transfer's W^c operand and one
+    partial batch of 2.  Every state equals, bit for bit, the same state
+    computed alone (the columns of the batched products are independent), and
+    all of them meet the oracle bar."""
+    import torch
+    shape = dict(n_k=3, n_b=64, R=513, N=129, n_occ=2, n_unocc=63)
+    inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=8, omega=gwsynth.omega_mesh("m16"))
+    n_occ = shape["n_occ"]
+    mesh = inp.omega
+    out = np.array([0.0, 0.3, 4.0])
+    states = [(k, b) for k in range(3) for b in (0, 1, 2, 5, 30, 64)]
+    mu = _mu(inp.eps, n_occ)
+    U64 = inp.U.astype(np.complex64).astype(np.complex128)
+    psi64 = inp.psi.astype(np.complex64).astype(np.complex128)
+    v = torch.from_numpy(inp.v).to("cuda")
+    Ws = _gpu_W(lib, torch.from_numpy(U64).to("cuda"), torch.from_numpy(psi64).to("cuda"), inp.eps, mesh, n_occ, v)
+    U32 = torch.from_numpy(inp.U).to("cuda", torch.complex64)
+    psi32 = torch.from_numpy(inp.psi).to("cuda", torch.complex64)
+    sig = lib.gw_sigma_c(U32, psi32, inp.eps, Ws, v, mesh, out, states, mu, precision="split_bf16").clone()
+    for i in (0, 15, 16, 17):
+        one = lib.gw_sigma_c(U32, psi32, inp.eps, Ws, v, mesh, out, [states[i]], mu, precision="split_bf16")
+        torch.cuda.synchronize()
+        assert torch.equal(sig[i], one[0]), i
+    ref = _oracle(U64, psi64, inp.eps, mesh, n_occ, inp.v, out, states, mu)
+    err = _rel(sig.cpu().numpy(), ref)
+    print(f"sigma_c split_bf16, 18 states in batches of 16 + 2: rel err {err:.2e}")
+    assert err < 1e-4
