@@ -147,9 +147,10 @@ int gw_polarization(void* stream, const gw_pol_desc* desc_host, void* ws, size_t
  *   P       [n_omega][N][N] c128, Hermitian (only the lower triangle is read)
  *   v       [N] doubles > 0
  *   W       [n_omega][N][N] c128 output (full Hermitian matrix); may not alias P
- *   info    [n_omega] ints (device), written: 0 on success, c+1 if the pivot
- *           block starting at column c was not positive definite (W_j is then
- *           undefined).  Read it after synchronising the stream. */
+ *   info    [n_omega] ints (device), written: 0 on success, c+1 if the
+ *           elimination met a non-positive (or non-finite) pivot at column c,
+ *           i.e. eps_j is not positive definite (W_j is then undefined).  Read
+ *           it after synchronising the stream. */
 int gw_screen_workspace_size(int N, int n_omega, size_t* bytes_host);
 int gw_screen(void* stream, int N, int n_omega, const double* P, const double* v, double* W,
               int* info, void* ws, size_t ws_bytes);
