@@ -121,6 +121,68 @@ def polarization(U, psi, eps, omega, n_occ: int, *, kq=None, k_list=None,
     return P
 
 
+def hat_weights(x, nodes) -> np.ndarray:
+    """h[b, t]: the share of a transition at energy x_t given to node b when
+    its spectral weight is split linearly between the two nodes around it
+    (x_t inside [nodes[0], nodes[-1]], nodes strictly increasing)."""
+    x = np.asarray(x, dtype=np.float64)
+    nd = np.asarray(nodes, dtype=np.float64)
+    if nd.ndim != 1 or nd.size < 2 or np.any(np.diff(nd) <= 0):
+        raise ValueError("nodes must increase strictly (at least two)")
+    if x.size and (x.min() < nd[0] or x.max() > nd[-1]):
+        raise ValueError("a transition energy lies outside the nodes")
+    h = np.zeros((nd.size, x.size))
+    for t, xt in enumerate(x):
+        b = min(int(np.searchsorted(nd, xt, side="right")) - 1, nd.size - 2)
+        f = (xt - nd[b]) / (nd[b + 1] - nd[b])
+        h[b, t] += 1.0 - f
+        h[b + 1, t] += f
+    return h
+
+
+def spectral_weights(U, psi, eps, n_occ: int, nodes, *, kq=None, k_list=None, occ_range=None,
+                     unocc_range=None) -> np.ndarray:
+    """S[b] = sum over the transitions of h_b(x_t) M_t M_t^H with x_t = e_n' - e_n
+    > 0: the spectral function of P (the imaginary part of Eq. polar_MB on the
+    real axis, a sum of delta functions at the transition energies) with every
+    delta moved onto the two nodes around it.  [n_nodes][N][N] complex128."""
+    U = np.asarray(U, dtype=np.complex128)
+    n_k = psi.shape[0]
+    n_unocc = psi.shape[1] - n_occ
+    kq = ((np.arange(n_k) + 1) % n_k) if kq is None else np.asarray(kq)
+    ks = range(n_k) if k_list is None else list(k_list)
+    o0, o1 = (0, n_occ) if occ_range is None else occ_range
+    u0, u1 = (0, n_unocc) if unocc_range is None else unocc_range
+    nd = np.asarray(nodes, dtype=np.float64)
+    N = U.shape[0]
+    S = np.zeros((nd.size, N, N), dtype=np.complex128)
+    for k in ks:
+        kk = int(kq[k])
+        po = np.asarray(psi[k, o0:o1], dtype=np.complex128)
+        pu = np.asarray(psi[kk, n_occ + u0:n_occ + u1], dtype=np.complex128)
+        M = projections(U, po, pu)
+        x = (np.asarray(eps[kk, n_occ + u0:n_occ + u1])[None, :] - np.asarray(eps[k, o0:o1])[:, None]).reshape(-1)
+        h = hat_weights(x, nd)
+        MH = M.conj().T
+        for b in range(nd.size):
+            S[b] += (M * h[b][None, :]) @ MH
+    return S
+
+
+def polarization_spectral(U, psi, eps, omega, n_occ: int, nodes, **kw) -> np.ndarray:
+    """P(i w) from the node spectral weights by the Hilbert transform of each
+    node's delta function (the route of the text after Eq. polar_MB):
+    P(i w) = sum_b -4 x_b / (x_b^2 + w^2) S[b], the same spin-summed bracket as
+    the direct sum evaluated at the node energy.  Exact when every transition
+    sits on a node; otherwise the bracket is interpolated linearly in x
+    between the nodes."""
+    S = spectral_weights(U, psi, eps, n_occ, nodes, **kw)
+    nd = np.asarray(nodes, dtype=np.float64)
+    om = np.asarray(omega, dtype=np.float64)
+    c = -4.0 * nd[None, :] / (nd[None, :] ** 2 + om[:, None] ** 2)      # [n_omega][n_nodes]
+    return np.einsum("jb,bxy->jxy", c, S)
+
+
 def screened_interaction(P: np.ndarray, v: np.ndarray) -> np.ndarray:
     """W = (1 - v P)^-1 v for diagonal v (Eq. W_Dyson in matrix form), per
     frequency, by LU solve of (I - diag(v) P) W = diag(v)."""
