@@ -69,6 +69,10 @@ def parse():
     ap.add_argument("--mpb", action="store_true",
                     help="basis optimization study instead: Sigma_c and time against the Coulomb-eigenvalue "
                          "threshold v_min on the training-run shapes")
+    ap.add_argument("--spectral", action="store_true",
+                    help="spectral route (transition-energy nodes + Hilbert transform) against the direct sum: time "
+                         "and error for 32..256 nodes at 64 imaginary frequencies, one k-point of the supercell "
+                         "workload")
     ap.add_argument("--surrogate-ablation", action="store_true",
                     help="ablation of the high-band correction on held-out training-run seeds: truncation, "
                          "missing diagonal only, congruence (learned and exact), and a rank-8 term in the "
@@ -125,6 +129,67 @@ def traffic_driver(a) -> int:
     call.run()
     torch.cuda.synchronize()
     print(json.dumps({"traffic_driver": a.workload, "pairs": shp.n_occ * cutoff, "precision": a.precision}))
+    return 0
+
+
+def spectral_bench(a) -> int:
+    """The spectral route against the direct sum on one k-point of the
+    supercell-shaped workload (N=3000, R=32768, 128 occupied x 2000 unoccupied
+    bands, split BF16): the direct sum at the 16-frequency mesh and at 64
+    frequencies, and the spectral route at the 64 frequencies with 32, 64, 128
+    and 256 log-spaced nodes over the transition energies; time of each call
+    and the relative Frobenius difference from the direct sum per frequency.
+    One JSON line."""
+    import numpy as np
+    import torch
+
+    import gwsynth
+    from paper_1003_0316_amd import binding as gw
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shp = gwsynth.SHAPES["c3"]
+    inp = gwsynth.generate_torch(shp, dev, k_subset=[0, 1], log=log)
+    n_occ = shp.n_occ
+    om16 = np.asarray(inp.omega, dtype=np.float64)
+    om64 = np.concatenate([[0.0], np.geomspace(0.01, 20.0, 63)])
+    x_lo = inp.eps[1, n_occ:].min() - inp.eps[0, :n_occ].max()
+    x_hi = inp.eps[1, n_occ:].max() - inp.eps[0, :n_occ].min()
+
+    def timed(omega, nodes=None):
+        call = gw.PolarizationCall(inp.U, inp.psi, inp.eps, omega, n_occ, precision="split_bf16", k_list=[0],
+                                   nodes=nodes)
+        ws = torch.empty(call.workspace_size(), dtype=torch.uint8, device=dev)
+        call.run(ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        P = call.run(ws)
+        e1.record()
+        torch.cuda.synchronize()
+        del ws
+        return P, e0.elapsed_time(e1) / 1e3
+
+    _, t16 = timed(om16)
+    log(f"direct sum, 16 frequencies: {t16:.3f} s")
+    Pd, t64 = timed(om64)
+    log(f"direct sum, 64 frequencies: {t64:.3f} s")
+    nd = torch.linalg.norm(Pd.reshape(om64.size, -1), dim=1)
+    rows = []
+    for B in (32, 64, 128, 256):
+        nodes = np.geomspace(x_lo, x_hi, B)
+        Ps, t = timed(om64, nodes)
+        err = (torch.linalg.norm((Ps - Pd).reshape(om64.size, -1), dim=1) / nd).cpu().numpy()
+        del Ps
+        torch.cuda.empty_cache()
+        rows.append({"nodes": B, "s": round(t, 3), "max_rel_diff": float(err.max()), "rel_diff_w0": float(err[0]),
+                     "rel_diff_wmax": float(err[-1])})
+        log(f"spectral route, {B} nodes: {t:.3f} s, max rel diff from the direct sum {err.max():.2e}")
+    print(json.dumps({"metric": "spectral route vs direct sum, s per k-point and relative difference of P",
+                      "unit": "s", "direct_16_freq_s": round(t16, 3), "direct_64_freq_s": round(t64, 3),
+                      "spectral_64_freq": rows, "transition_energy_range": [float(x_lo), float(x_hi)],
+                      "config": {"workload": "c3 shapes, k = 0 (unoccupied bands of set 1): N=3000, R=32768, "
+                                             "128 x 2000 pairs", "precision": "split_bf16",
+                                 "nodes": "log-spaced over the transition energies"}}))
     return 0
 
 
@@ -519,6 +584,8 @@ def main() -> int:
         return mpb_bench(a)
     if a.surrogate_ablation:
         return surrogate_ablation(a)
+    if a.spectral:
+        return spectral_bench(a)
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported: this build runs on one GPU only "
               f"(the k-point / occupied-band shards and the reduce-scatter of P over frequencies are "

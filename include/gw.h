@@ -111,7 +111,22 @@ int gw_project(void* stream, int precision, int N, int R, int n_occ, int n_unocc
  * are real float32 arrays of the same shapes -- the inversion-symmetric case,
  * where a symmetrized basis makes the matrices real symmetric (Sec. "Mixed
  * product basis", Eq. condition_inv; the text after Eq. polar_MB).  Every product and P are then real; P is returned as c128 with zero
- * imaginary parts, and the contractions need a quarter of the MFMA work. */
+ * imaginary parts, and the contractions need a quarter of the MFMA work.
+ *
+ * n_nodes > 0 selects the spectral route of the text after Eq. polar_MB: the
+ * spectral function (the imaginary part of P on the real axis, a delta
+ * function at every transition energy x = eps_kq[n'] - eps_k[n]) is
+ * accumulated on the transition-energy nodes nodes_host[0..n_nodes), each
+ * transition's weight split linearly between the two nodes around x, and
+ * P(i w_j) is the Hilbert transform of the node weights:
+ *   P(i w_j) = sum_b -4 x_b / (x_b^2 + w_j^2) sum_t h_b(x_t) M_t M_t^H.
+ * It is exact when every transition sits on a node and otherwise interpolates
+ * the bracket linearly in x between nodes (error falling as the square of the
+ * node spacing).  2 <= n_nodes <= 256 (<= 64 with GW_SPLIT_FP16), nodes
+ * finite, > 0 and increasing, and every summed transition energy inside
+ * [nodes[0], nodes[n_nodes-1]], else GW_ERR_INVALID_ARG (GW_ERR_UNSUPPORTED
+ * for the node count with GW_SPLIT_FP16).  The workspace then also holds the
+ * n_nodes node matrices (n_nodes * N * N * 16 bytes). */
 typedef struct gw_pol_desc {
   int precision;            /* gw_precision */
   int n_k;                  /* k-sets held in psi / eps */
@@ -133,6 +148,8 @@ typedef struct gw_pol_desc {
   int accumulate;           /* 0: P is overwritten; 1: the sum is added to P */
   int chunk_pairs;          /* transition pairs per chunk; 0 = library default */
   int real_inputs;          /* 1: U and psi are real float32 (see above); 0: complex */
+  int n_nodes;              /* > 0: spectral route on these nodes (see above); 0: direct sum */
+  const double* nodes_host; /* [n_nodes] transition-energy nodes (Hartree), increasing */
 } gw_pol_desc;
 
 int gw_polarization_workspace_size(const gw_pol_desc* desc_host, size_t* bytes_host);

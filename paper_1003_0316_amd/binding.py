@@ -51,6 +51,7 @@ class GwPolDesc(ctypes.Structure):
         ("P", ctypes.c_void_p),
         ("accumulate", ctypes.c_int), ("chunk_pairs", ctypes.c_int),
         ("real_inputs", ctypes.c_int),
+        ("n_nodes", ctypes.c_int), ("nodes_host", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -223,7 +224,7 @@ class PolarizationCall:
 
     def __init__(self, U, psi, eps_host, omega, n_occ, *, precision="fp64", eps_dev=None, P=None,
                  k_list=None, kq=None, occ_range=None, unocc_range=None, accumulate=False, chunk_pairs=0,
-                 real=False):
+                 real=False, nodes=None):
         prec = _prec(precision)
         dt = torch.float32 if real else _cdtype(prec)
         _dev_tensor(U, "U", dt)
@@ -271,6 +272,13 @@ class PolarizationCall:
         d.accumulate = 1 if accumulate else 0
         d.chunk_pairs = int(chunk_pairs)
         d.real_inputs = 1 if real else 0
+        self.nodes = None if nodes is None else np.ascontiguousarray(nodes, dtype=np.float64)
+        if self.nodes is not None:
+            d.n_nodes = int(self.nodes.shape[0])
+            d.nodes_host = self.nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            d.n_nodes = 0
+            d.nodes_host = None
         self.desc = d
 
     def workspace_size(self) -> int:
@@ -287,7 +295,8 @@ class PolarizationCall:
 
 
 def gw_polarization(U, psi, eps_host, omega, n_occ, **kw) -> torch.Tensor:
-    """P[j] = sum_k sum_{n occ} sum_{n' unocc} w M M^H (see gw.h).  Returns P
+    """P[j] = sum_k sum_{n occ} sum_{n' unocc} w M M^H (see gw.h); with
+    nodes=[...] the spectral route on those transition-energy nodes.  Returns P
     (complex128 [n_omega][N][N]); the work is enqueued on the current stream."""
     ws = kw.pop("ws", None)
     stream = kw.pop("stream", None)

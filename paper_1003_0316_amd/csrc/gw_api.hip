@@ -43,7 +43,33 @@ int default_chunk_pairs(const gw_pol_desc& d) {
   return mfma_default_chunk_pairs(d.N, d.R, d.n_omega, d.precision);
 }
 
+// The polarization pass of the spectral route: the node energies are its
+// accumulation slots, the node matrices (in the workspace) its output.
+gw_pol_desc spectral_inner(const gw_pol_desc& d, double2* S) {
+  gw_pol_desc in = d;
+  in.n_omega = d.n_nodes;
+  in.omega_host = d.nodes_host;
+  in.P = reinterpret_cast<double*>(S);
+  in.accumulate = 0;
+  in.n_nodes = 0;
+  in.nodes_host = nullptr;
+  return in;
+}
+
+size_t node_bytes(const gw_pol_desc& d) { return align_up((size_t)d.n_nodes * d.N * d.N * 16); }
+
+Plan make_plan_direct(const gw_pol_desc& d);
+
 Plan make_plan(const gw_pol_desc& d) {
+  if (d.n_nodes > 0) {
+    Plan pl = make_plan_direct(spectral_inner(d, nullptr));
+    pl.ws += node_bytes(d);
+    return pl;
+  }
+  return make_plan_direct(d);
+}
+
+Plan make_plan_direct(const gw_pol_desc& d) {
   Plan pl;
   const long total = (long)(d.occ_end - d.occ_begin) * (d.unocc_end - d.unocc_begin);
   pl.tc = (int)std::max(1L, std::min<long>(default_chunk_pairs(d), total));
@@ -90,6 +116,17 @@ int validate_desc(const gw_pol_desc* dp) {
       if (d.k_list_host[i] < 0 || d.k_list_host[i] >= d.n_k)
         return fail(GW_ERR_INVALID_ARG, "gw_polarization: k_list_host entry out of range");
   }
+  if (d.n_nodes < 0) return fail(GW_ERR_INVALID_ARG, "gw_polarization: n_nodes < 0");
+  if (d.n_nodes > 0) {
+    if (d.n_nodes < 2 || d.n_nodes > kMaxSlots)
+      return fail(GW_ERR_INVALID_ARG, "gw_polarization: the spectral route needs 2..256 nodes");
+    if (d.precision == GW_SPLIT_FP16 && d.n_nodes > kMaxOmega)
+      return fail(GW_ERR_UNSUPPORTED, "gw_polarization: at most 64 nodes with GW_SPLIT_FP16");
+    if (!d.nodes_host) return fail(GW_ERR_INVALID_ARG, "gw_polarization: nodes_host is NULL");
+    for (int b = 0; b < d.n_nodes; ++b)
+      if (!std::isfinite(d.nodes_host[b]) || d.nodes_host[b] <= 0.0 || (b > 0 && d.nodes_host[b] <= d.nodes_host[b - 1]))
+        return fail(GW_ERR_INVALID_ARG, "gw_polarization: nodes must be finite, > 0 and increasing");
+  }
   // Insulator: every summed occupied level below every summed unoccupied level at k+q.
   const int nb = d.n_occ + d.n_unocc;
   const int nk = d.k_list_host ? d.n_k_list : d.n_k;
@@ -115,10 +152,78 @@ int validate_desc(const gw_pol_desc* dp) {
                k, hi, lo);
       return fail(GW_ERR_INVALID_ARG, buf);
     }
+    if (d.n_nodes > 0) {
+      // transition energies of this k lie in [lo - hi, top - bottom]
+      double bottom = INFINITY, top = -INFINITY;
+      for (int n = d.occ_begin; n < d.occ_end; ++n) bottom = std::min(bottom, d.eps_host[(size_t)k * nb + n]);
+      for (int u = d.unocc_begin; u < d.unocc_end; ++u) top = std::max(top, d.eps_host[(size_t)kq * nb + d.n_occ + u]);
+      if (lo - hi < d.nodes_host[0] || top - bottom > d.nodes_host[d.n_nodes - 1]) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "gw_polarization: k=%d: transition energies [%.6g, %.6g] are not inside the nodes [%.6g, %.6g]", k,
+                 lo - hi, top - bottom, d.nodes_host[0], d.nodes_host[d.n_nodes - 1]);
+        return fail(GW_ERR_INVALID_ARG, buf);
+      }
+    }
   }
   return GW_OK;
 }
 
+// One pass of the direct sum into the slots of d (frequencies, or the nodes of
+// the spectral route when hat = 1); validated arguments, sized workspace.
+int polarization_pass(hipStream_t s, const gw_pol_desc& d, int hat, void* ws) {
+  int st;
+  Plan pl = make_plan_direct(d);
+  OmegaList om;
+  om.n = d.n_omega;
+  om.hat = hat;
+  for (int j = 0; j < kMaxSlots; ++j) om.w[j] = j < d.n_omega ? d.omega_host[j] : 0.0;
+  const int nb = d.n_occ + d.n_unocc;
+  const size_t NN = (size_t)d.N * d.N;
+  double2* P = reinterpret_cast<double2*>(d.P);
+  if (!d.accumulate) {
+    st = launch_fill_zero(s, d.P, NN * 2 * d.n_omega);
+    if (st != GW_OK) return st;
+  }
+  std::vector<Chunk> chunks;
+  const int nk = d.k_list_host ? d.n_k_list : d.n_k;
+  for (int i = 0; i < nk; ++i) {
+    int k = d.k_list_host ? d.k_list_host[i] : i;
+    int kq = d.kq_host ? d.kq_host[k] : (k + 1) % d.n_k;
+    const int nu = d.unocc_end - d.unocc_begin;
+    const long total = (long)(d.occ_end - d.occ_begin) * nu;
+    for (long tb = 0; tb < total; tb += pl.tc) {
+      Chunk c;
+      c.k = k;
+      c.kq = kq;
+      c.n0 = d.occ_begin;
+      c.u0 = d.unocc_begin;
+      c.nu = nu;
+      c.tb = tb;
+      c.T = (int)std::min<long>(pl.tc, total - tb);
+      chunks.push_back(c);
+    }
+  }
+  if (d.precision == GW_FP64) {
+    Carver cv(ws);
+    double2* M = cv.take<double2>((size_t)d.N * pl.tc);
+    double* w = cv.take<double>((size_t)d.n_omega * pl.tc);
+    const double2* U = static_cast<const double2*>(d.U);
+    const double2* psi = static_cast<const double2*>(d.psi);
+    for (const Chunk& c : chunks) {
+      const double2* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
+      const double2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
+      if ((st = launch_weights_f64(s, d.eps, nb, d.n_occ, c, om, w)) != GW_OK) return st;
+      if ((st = launch_project_f64(s, d.N, d.R, U, po, pu, c.nu, c.tb, c.T, M, c.T)) != GW_OK) return st;
+      if ((st = launch_herk_f64(s, d.N, c.pairs(), M, c.pairs(), w, d.n_omega, P)) != GW_OK) return st;
+    }
+  } else {
+    st = d.real_inputs ? tiled_polarization_real(s, d, chunks, pl.tc, om, ws)
+                       : mfma_polarization(s, d, chunks, pl.tc, om, ws);
+    if (st != GW_OK) return st;
+  }
+  return launch_hermitian_mirror(s, d.N, d.n_omega, P);
+}
 }  // namespace
 }  // namespace gw
 
@@ -169,6 +274,10 @@ int gw_polarization_workspace_size(const gw_pol_desc* d, size_t* bytes) {
     return fail(GW_ERR_INVALID_ARG, "gw_polarization: real_inputs must be 0 or 1");
   if (d->real_inputs && d->precision != GW_SPLIT_BF16)
     return fail(GW_ERR_UNSUPPORTED, "gw_polarization: real inputs are supported with GW_SPLIT_BF16 only");
+  if (d->n_nodes < 0 || d->n_nodes == 1 || d->n_nodes > kMaxSlots)
+    return fail(GW_ERR_INVALID_ARG, "gw_polarization: the spectral route needs 2..256 nodes");
+  if (d->n_nodes > kMaxOmega && d->precision == GW_SPLIT_FP16)
+    return fail(GW_ERR_UNSUPPORTED, "gw_polarization: at most 64 nodes with GW_SPLIT_FP16");
   *bytes = make_plan(*d).ws;
   return GW_OK;
 }
@@ -184,54 +293,17 @@ int gw_polarization(void* stream, const gw_pol_desc* dp, void* ws, size_t ws_byt
     return fail(GW_ERR_WORKSPACE, buf);
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  OmegaList om;
-  om.n = d.n_omega;
-  for (int j = 0; j < kMaxOmega; ++j) om.w[j] = j < d.n_omega ? d.omega_host[j] : 0.0;
-  const int nb = d.n_occ + d.n_unocc;
-  const size_t NN = (size_t)d.N * d.N;
-  double2* P = reinterpret_cast<double2*>(d.P);
-  if (!d.accumulate) {
-    st = launch_fill_zero(s, d.P, NN * 2 * d.n_omega);
-    if (st != GW_OK) return st;
-  }
-  std::vector<Chunk> chunks;
-  const int nk = d.k_list_host ? d.n_k_list : d.n_k;
-  for (int i = 0; i < nk; ++i) {
-    int k = d.k_list_host ? d.k_list_host[i] : i;
-    int kq = d.kq_host ? d.kq_host[k] : (k + 1) % d.n_k;
-    const int nu = d.unocc_end - d.unocc_begin;
-    const long total = (long)(d.occ_end - d.occ_begin) * nu;
-    for (long tb = 0; tb < total; tb += pl.tc) {
-      Chunk c;
-      c.k = k;
-      c.kq = kq;
-      c.n0 = d.occ_begin;
-      c.u0 = d.unocc_begin;
-      c.nu = nu;
-      c.tb = tb;
-      c.T = (int)std::min<long>(pl.tc, total - tb);
-      chunks.push_back(c);
-    }
-  }
-  if (d.precision == GW_FP64) {
-    Carver cv(ws);
-    double2* M = cv.take<double2>((size_t)d.N * pl.tc);
-    double* w = cv.take<double>((size_t)d.n_omega * pl.tc);
-    const double2* U = static_cast<const double2*>(d.U);
-    const double2* psi = static_cast<const double2*>(d.psi);
-    for (const Chunk& c : chunks) {
-      const double2* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
-      const double2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
-      if ((st = launch_weights_f64(s, d.eps, nb, d.n_occ, c, om, w)) != GW_OK) return st;
-      if ((st = launch_project_f64(s, d.N, d.R, U, po, pu, c.nu, c.tb, c.T, M, c.T)) != GW_OK) return st;
-      if ((st = launch_herk_f64(s, d.N, c.pairs(), M, c.pairs(), w, d.n_omega, P)) != GW_OK) return st;
-    }
-  } else {
-    st = d.real_inputs ? tiled_polarization_real(s, d, chunks, pl.tc, om, ws)
-                       : mfma_polarization(s, d, chunks, pl.tc, om, ws);
-    if (st != GW_OK) return st;
-  }
-  return launch_hermitian_mirror(s, d.N, d.n_omega, P);
+  if (d.n_nodes == 0) return polarization_pass(s, d, 0, ws);
+  // spectral route: node matrices first (workspace head), then their transform
+  double2* S = static_cast<double2*>(ws);
+  const gw_pol_desc in = spectral_inner(d, S);
+  if ((st = polarization_pass(s, in, 1, static_cast<char*>(ws) + node_bytes(d))) != GW_OK) return st;
+  OmegaList nodes;
+  nodes.n = d.n_nodes;
+  nodes.hat = 1;
+  for (int b = 0; b < kMaxSlots; ++b) nodes.w[b] = b < d.n_nodes ? d.nodes_host[b] : 0.0;
+  return launch_spectral_combine(s, d.N, nodes, d.n_omega, d.omega_host, S, reinterpret_cast<double2*>(d.P),
+                                 d.accumulate);
 }
 
 int gw_screen_workspace_size(int N, int n_omega, size_t* bytes) {

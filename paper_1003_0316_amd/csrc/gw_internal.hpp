@@ -25,11 +25,30 @@ int hip_fail(hipError_t e, const char* what);          // GW_ERR_HIP with the HI
     if (e_ != hipSuccess) return ::gw::hip_fail(e_, what);    \
   } while (0)
 
-constexpr int kMaxOmega = 64;
+constexpr int kMaxOmega = 64;   // imaginary frequencies per call
+constexpr int kMaxSlots = 256;  // accumulation slots: frequencies, or the energy nodes of the spectral route
+// The slots a polarization pass accumulates into.  hat == 0: slot j is the
+// imaginary frequency w[j]; hat == 1: slot j is the transition-energy node
+// w[j] of the spectral route (increasing).
 struct OmegaList {
   int n;
-  double w[kMaxOmega];
+  int hat = 0;
+  double w[kMaxSlots];
 };
+
+// Weight of a transition with D = e_occ - e_unocc < 0 in slot j: the
+// spin-summed imaginary-axis bracket of Eq. polar_MB, 4 D / (D^2 + w_j^2), or,
+// on the spectral route, minus the share of the transition's spectral weight
+// that goes to node j when it is split linearly between the two nodes around
+// x = -D.
+__device__ inline double pair_weight(double d, const OmegaList& om, int j) {
+  if (!om.hat) return 4.0 * d / (d * d + om.w[j] * om.w[j]);
+  const double x = -d, xj = om.w[j];
+  if (j > 0 && x >= om.w[j - 1] && x <= xj) return -(x - om.w[j - 1]) / (xj - om.w[j - 1]);
+  if (j + 1 < om.n && x > xj && x <= om.w[j + 1]) return -(om.w[j + 1] - x) / (om.w[j + 1] - xj);
+  if (j == 0 && x == xj) return -1.0;
+  return 0.0;
+}
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -74,6 +93,12 @@ struct Chunk {
   int T;
   int pairs() const { return T; }
 };
+
+// ---- spectral route (k_fp64.hip) -------------------------------------------------
+// P[j] (+)= sum_b 4 x_b / (x_b^2 + omega_j^2) S[b] over all N x N elements; S
+// holds the node accumulations (-S_b), [n_nodes][N][N].
+int launch_spectral_combine(hipStream_t s, int N, const OmegaList& nodes, int n_omega, const double* omega_host,
+                            const double2* S, double2* P, int accumulate);
 
 // ---- FP64 path (k_fp64.hip) ----------------------------------------------------
 int launch_fill_zero(hipStream_t s, double* p, size_t n_doubles);

@@ -1,6 +1,8 @@
 // FP64 path: transition weights, fused product + projection, weighted Hermitian
 // accumulation, Hermitian mirror.  Plain FP64 FMA with LDS tiling (on gfx950
 // the FP64 vector rate equals the FP64 matrix-core rate).
+#include <algorithm>
+
 #include "gw_internal.hpp"
 
 namespace gw {
@@ -17,8 +19,9 @@ __global__ void fill_zero_kernel(double* __restrict__ p, size_t n) {
   for (; i < n; i += stride) p[i] = 0.0;
 }
 
-// w[j][t] = 4 D / (D^2 + w_j^2), D = eps_k[n] - eps_kq[n_occ + u]: the
-// imaginary-axis bracket of Eq. polar_MB summed over two spins.
+// w[j][t] = pair_weight: 4 D / (D^2 + w_j^2), D = eps_k[n] - eps_kq[n_occ + u],
+// the imaginary-axis bracket of Eq. polar_MB summed over two spins (or the
+// node share of the spectral route).
 __global__ void weights_f64_kernel(const double* __restrict__ eps, int n_bands, int n_occ, Chunk c,
                                    OmegaList om, double* __restrict__ w) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -28,8 +31,7 @@ __global__ void weights_f64_kernel(const double* __restrict__ eps, int n_bands, 
   int n = c.n0 + (int)(g / c.nu);
   int u = c.u0 + (int)(g % c.nu);
   double d = eps[(size_t)c.k * n_bands + n] - eps[(size_t)c.kq * n_bands + n_occ + u];
-  double d2 = d * d;
-  for (int j = 0; j < om.n; ++j) w[(size_t)j * T + t] = 4.0 * d / (d2 + om.w[j] * om.w[j]);
+  for (int j = 0; j < om.n; ++j) w[(size_t)j * T + t] = pair_weight(d, om, j);
 }
 
 // M[I][t] = sum_r U[I][r] conj(po[n][r]) pu[u][r],  t = n*nu + u  (Eq. proj_MB).
@@ -260,6 +262,69 @@ int launch_hermitian_mirror(hipStream_t s, int N, int n_omega, double2* P) {
   dim3 grid(nb * (nb + 1) / 2, n_omega);
   hipLaunchKernelGGL(mirror_kernel, grid, dim3(256), 0, s, N, P);
   GW_LAUNCHED("mirror_kernel");
+  return GW_OK;
+}
+
+
+namespace {
+struct FreqList {
+  int n;
+  double w[kMaxOmega];
+};
+
+// Spectral route: P[j][e] (+)= sum_b c_jb S[b][e] with c_jb = 4 x_b / (x_b^2 +
+// omega_j^2), the imaginary-axis Hilbert transform of a delta function of
+// spectral weight at node energy x_b (S holds minus the node weights).  Block
+// row blockIdx.y covers frequencies 8 y .. 8 y + 7; their coefficients sit in
+// LDS; every element of S is read once per block row.
+constexpr int SC_J = 8;
+__global__ __launch_bounds__(256) void spectral_combine_kernel(size_t NN, OmegaList nodes, FreqList freq,
+                                                               const double2* __restrict__ S,
+                                                               double2* __restrict__ P, int accumulate) {
+  __shared__ double c[SC_J][kMaxSlots];
+  const int j0 = blockIdx.y * SC_J;
+  const int nj = min(SC_J, freq.n - j0);
+  for (int e = threadIdx.x; e < SC_J * nodes.n; e += blockDim.x) {
+    const int jj = e / nodes.n, b = e % nodes.n;
+    const double x = nodes.w[b], om = jj < nj ? freq.w[j0 + jj] : 0.0;
+    c[jj][b] = 4.0 * x / (x * x + om * om);
+  }
+  __syncthreads();
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < NN; e += (size_t)gridDim.x * blockDim.x) {
+    double2 acc[SC_J];
+#pragma unroll
+    for (int jj = 0; jj < SC_J; ++jj) acc[jj] = make_double2(0.0, 0.0);
+    for (int b = 0; b < nodes.n; ++b) {
+      const double2 v = S[(size_t)b * NN + e];
+#pragma unroll
+      for (int jj = 0; jj < SC_J; ++jj) {
+        acc[jj].x = fma(c[jj][b], v.x, acc[jj].x);
+        acc[jj].y = fma(c[jj][b], v.y, acc[jj].y);
+      }
+    }
+    for (int jj = 0; jj < nj; ++jj) {
+      double2* p = P + (size_t)(j0 + jj) * NN + e;
+      if (accumulate) {
+        const double2 o = *p;
+        *p = make_double2(o.x + acc[jj].x, o.y + acc[jj].y);
+      } else {
+        *p = acc[jj];
+      }
+    }
+  }
+}
+}  // namespace
+
+int launch_spectral_combine(hipStream_t s, int N, const OmegaList& nodes, int n_omega, const double* omega_host,
+                            const double2* S, double2* P, int accumulate) {
+  FreqList f{};
+  f.n = n_omega;
+  for (int j = 0; j < n_omega; ++j) f.w[j] = omega_host[j];
+  const size_t NN = (size_t)N * N;
+  const unsigned gx = (unsigned)std::min<size_t>((NN + 255) / 256, 2048);
+  hipLaunchKernelGGL(spectral_combine_kernel, dim3(gx, (n_omega + SC_J - 1) / SC_J), dim3(256), 0, s, NN, nodes, f,
+                     S, P, accumulate);
+  GW_LAUNCHED("spectral_combine_kernel");
   return GW_OK;
 }
 

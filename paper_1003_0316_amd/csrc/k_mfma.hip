@@ -234,7 +234,7 @@ __global__ __launch_bounds__(NT, 2) void herk_f32_kernel(int N, int T, const flo
     }
 }
 
-// w[j][t] = 4 D / (D^2 + w_j^2) evaluated in FP64, stored as float.
+// w[j][t] = pair_weight (as in the FP64 path) evaluated in FP64, stored as float.
 __global__ void weights_f32_kernel(const double* __restrict__ eps, int n_bands, int n_occ, Chunk c, OmegaList om,
                                    float* __restrict__ w) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,8 +244,7 @@ __global__ void weights_f32_kernel(const double* __restrict__ eps, int n_bands, 
   int n = c.n0 + (int)(g / c.nu);
   int u = c.u0 + (int)(g % c.nu);
   double d = eps[(size_t)c.k * n_bands + n] - eps[(size_t)c.kq * n_bands + n_occ + u];
-  double d2 = d * d;
-  for (int j = 0; j < om.n; ++j) w[(size_t)j * T + t] = (float)(4.0 * d / (d2 + om.w[j] * om.w[j]));
+  for (int j = 0; j < om.n; ++j) w[(size_t)j * T + t] = (float)pair_weight(d, om, j);
 }
 
 int launch_project_f32(hipStream_t s, int N, int R, const float2* U, const float2* po, const float2* pu, int nu,
@@ -660,7 +659,7 @@ __global__ void weights_f32_max_kernel(const double* __restrict__ eps, int n_ban
   for (int j = 0; j < om.n; ++j) {
     float x = 0.f;
     if (t < T) {
-      x = (float)(4.0 * d / (d * d + om.w[j] * om.w[j]));
+      x = (float)pair_weight(d, om, j);
       w[(size_t)j * T + t] = x;
     }
     red[threadIdx.x] = fabsf(x);

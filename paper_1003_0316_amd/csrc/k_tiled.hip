@@ -166,8 +166,9 @@ __global__ __launch_bounds__(256) void pair_product_kernel(int R, int nst, int n
   }
 }
 
-// s_j(t) = sqrt(-w_j(t)), w_j(t) = 4 D / (D^2 + omega_j^2), D = eps_n - eps_n' < 0
-// (FP64, Eq. polar_MB weights), zero for the padding pairs t in [T, Tp).
+// s_j(t) = sqrt(-w_j(t)) with w_j(t) = pair_weight (4 D / (D^2 + omega_j^2),
+// D = eps_n - eps_n' < 0, or a spectral-route node share), FP64, zero for the
+// padding pairs t in [T, Tp).
 __global__ void weights_sqrt_kernel(const double* __restrict__ eps, int n_bands, int n_occ, Chunk c, OmegaList om,
                                     int Tp, float* __restrict__ sw) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -180,7 +181,7 @@ __global__ void weights_sqrt_kernel(const double* __restrict__ eps, int n_bands,
     d = eps[(size_t)c.k * n_bands + n] - eps[(size_t)c.kq * n_bands + n_occ + u];
   }
   for (int j = 0; j < om.n; ++j) {
-    const double w = t < c.T ? 4.0 * d / (d * d + om.w[j] * om.w[j]) : 0.0;
+    const double w = t < c.T ? pair_weight(d, om, j) : 0.0;
     sw[(size_t)j * Tp + t] = (float)sqrt(fmax(-w, 0.0));
   }
 }

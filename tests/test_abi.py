@@ -239,3 +239,35 @@ def test_basis_select_count(b):
     v[2] = np.inf
     assert L.gw_basis_select_count(5, ptr, 1.0, ctypes.byref(n)) == -1
     assert L.gw_basis_select(None, 4, 4, 12, 1, 1, 0.0, 1, 1, 1, 1) == -1      # element size
+
+
+def _with_nodes(d, keep, nodes):
+    keep["nodes"] = np.ascontiguousarray(nodes, dtype=np.float64)
+    d.n_nodes = len(nodes)
+    d.nodes_host = keep["nodes"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def test_spectral_route_validation(b):
+    """Transition energies of the default descriptor span [0.2, 1.5]."""
+    L = b.lib()
+    out = ctypes.c_size_t(0)
+    d, keep = _desc(b)
+    assert L.gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 0
+    direct = out.value
+    _with_nodes(d, keep, [0.2, 0.5, 1.5])
+    assert L.gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 0
+    assert out.value >= direct + 3 * 8 * 8 * 16                   # the node matrices
+    st = L.gw_polarization(None, ctypes.byref(d), ctypes.c_void_p(0x7F0000002000), 16)
+    assert st == -3                                               # arguments valid, workspace too small
+    for bad in ([0.25, 0.5, 1.5], [0.2, 0.5, 1.4], [0.2, 0.2, 1.5], [0.0, 0.5, 1.5], [0.2], [1.5, 0.5, 0.2]):
+        d, keep = _desc(b)
+        _with_nodes(d, keep, bad)
+        assert _status(b, d) == -1, bad
+        assert "node" in b.gw_last_error()
+    d, keep = _desc(b)
+    _with_nodes(d, keep, np.linspace(0.2, 1.5, 257))
+    assert L.gw_polarization_workspace_size(ctypes.byref(d), ctypes.byref(out)) == -1
+    assert _status(b, d) == -1
+    d, keep = _desc(b, precision=3)                               # split FP16: at most 64 nodes
+    _with_nodes(d, keep, np.linspace(0.2, 1.5, 65))
+    assert _status(b, d) == -2
