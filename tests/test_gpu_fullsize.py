@@ -103,3 +103,27 @@ def test_largest_size_sampled_with_screening(lib):
         worst = max(worst, float(torch.linalg.norm(lhs - rhs) / torch.linalg.norm(rhs)))
     print(f"c5 screening: max relative residual of (1 - vP) W = v on the sampled rows {worst:.2e}")
     assert worst < 1e-10
+
+
+def test_largest_size_top_bands_sampled(lib):
+    """N_k=4, N=6000, R=65536, 16 frequencies, the explicit bands of the
+    surrogate path: k = 2 with the six highest occupied bands (250..255, the
+    smallest gaps and largest weights), unoccupied bands 0..1499 of set 3,
+    split BF16, sampled block against the oracle."""
+    import torch
+    shp = gwsynth.SHAPES["c5"]
+    cut = shp.n_unocc_cut
+    nb = shp.n_occ + cut
+    inp = gwsynth.generate_torch(shp, torch.device("cuda"), k_subset=[2, 3], band_limit=nb)
+    eps = np.ascontiguousarray(inp.eps[:, :nb])
+    occ = (shp.n_occ - 6, shp.n_occ)
+    P = lib.gw_polarization(inp.U, inp.psi, eps, inp.omega, shp.n_occ, precision="split_bf16", k_list=[2],
+                            occ_range=occ)
+    torch.cuda.synchronize()
+    S = _sample_rows(shp.N, seed=2)
+    Pg = _block(P, S)
+    del P
+    ref = _oracle_block(inp.U, inp.psi, eps, inp.omega, shp.n_occ, [2, 3], [1, 0], [0], occ, (0, cut), S)
+    err = orc.rel_fro(Pg, ref)
+    print(f"c5 split_bf16, k=2, top occupied bands: sampled P max rel err {err.max():.2e}")
+    assert err.max() < TOL
