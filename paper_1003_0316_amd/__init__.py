@@ -13,6 +13,9 @@ __all__ = ["binding", "build"]
 def __getattr__(name):
     if name.startswith("__"):
         raise AttributeError(name)
+    if name in ("build", "surrogate", "train_surrogate"):
+        # submodules; the build step must work before the library exists
+        return importlib.import_module(__name__ + "." + name)
     b = importlib.import_module(__name__ + ".binding")
     if name == "binding":
         return b
