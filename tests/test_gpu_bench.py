@@ -1,0 +1,35 @@
+"""bench.py's output contract on a small workload (config 2 shapes): one JSON
+line with the keys the measurement is read from, a roofline object for the
+dominant kernel and the oracle's CPU baseline."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_json_contract_small_workload():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "c2", "--cpu-seconds", "2"],
+                       capture_output=True, text=True, timeout=900, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1, r.stdout
+    d = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["higher_is_better"] is False and d["value"] > 0
+    assert d["config"]["workload"].startswith("c2")
+    rf = d["roofline"]
+    assert rf["bound"] in ("mfma", "hbm", "alu")
+    assert rf["unit"] in ("TFLOP/s", "GB/s")
+    assert rf["achieved"] > 0 and rf["peak"] > 0 and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
+    assert "traffic" in rf
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
+    assert d["parity"]["max_rel_fro_err"] < 1e-4
+    print(f"c2 bench line: {d['value']} {d['unit']}, dominant kernel {rf['kernel']} at {rf['achieved']} {rf['unit']}")
