@@ -760,6 +760,15 @@ def main() -> int:
         # cpu baseline: the oracle on one occupied band x m unoccupied bands (full basis)
         U_h = U.cpu().numpy().astype(np.complex128)
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        blas = "unknown BLAS"
+        try:   # the oracle's products run in NumPy's BLAS: report its thread count
+            import threadpoolctl
+            pools = [p for p in threadpoolctl.threadpool_info() if p.get("user_api") == "blas"]
+            if pools:
+                cores = max(int(p["num_threads"]) for p in pools)
+                blas = f"{pools[0].get('internal_api')} BLAS, {cores} threads"
+        except ImportError:
+            pass
         def oracle_time(m):
             tc = time.time()
             orc.polarization(U_h, psi_h, inp.eps, inp.omega, shp.n_occ, kq=inp.kq, k_list=[0], occ_range=(0, 1),
@@ -777,7 +786,8 @@ def main() -> int:
         scale = T_pairs / (o2 * m2)
         cpu = {"value": round(dt2 * scale, 1), "unit": "s/q-point", "cores": cores, "kind": "oracle",
                "sample": f"k=0, occupied 0..{o2 - 1} x unoccupied 0..{m2 - 1} ({o2 * m2} pairs, full basis, all "
-                         f"{n_om} frequencies) in {dt2:.1f} s, scaled x{scale:.0f} to the {T_pairs} pairs of a q-point"}
+                         f"{n_om} frequencies) in {dt2:.1f} s ({blas}), scaled x{scale:.0f} to the {T_pairs} pairs "
+                         f"of a q-point"}
         log(f"cpu oracle: {dt2:.1f} s for {o2 * m2} pairs -> {dt2 * scale:.0f} s/q-point extrapolated")
         del U_h
 

@@ -32,4 +32,4 @@ def test_bench_json_contract_small_workload():
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
     assert d["parity"]["max_rel_fro_err"] < 1e-4
-    print(f"c2 bench line: {d['value']} {d['unit']}, dominant kernel {rf['kernel']} at {rf['achieved']} {rf['unit']}")
+    print(f"c2 bench line: {d['value']} {d['unit']}, dominant kernel {rf['kernel']} at {rf['achieved']} {rf['unit']}; cpu baseline {cb}")
