@@ -27,9 +27,12 @@ Two backends draw the same recipe:
 * ``torch`` -- for the large workloads: the Gaussian arrays (A, z, U) are drawn
   on the device with torch's counter-based generator seeded from the same
   SeedSequence children; the energies still come from numpy on the host.  z is
-  orthonormalised by a complex128 QR and z^T A runs in complex64, both on the
-  device.  Values differ from the numpy backend; each run's oracle consumes the
-  very tensors the GPU path consumes.
+  orthonormalised in complex128 on the device by shifted Cholesky QR (three
+  passes of Gram matrix, Cholesky factor and triangular solve, every step a
+  matrix product except the factorisation and inversion of small diagonal
+  blocks, done by host LAPACK), so no device solver library is involved; z^T A
+  runs in complex64 on the device.  Values differ from the numpy backend; each
+  run's oracle consumes the very tensors the GPU path consumes.
 """
 from __future__ import annotations
 
@@ -124,6 +127,81 @@ def _orthonormal_columns(zraw: np.ndarray) -> np.ndarray:
     return out
 
 
+
+def _cholesky_lower(G, block: int = 512):
+    """Lower Cholesky factor L (G = L L^H) of a Hermitian positive definite
+    torch matrix, blocked right-looking: each diagonal block is factored and
+    inverted by host LAPACK; the panel and the trailing update are matrix
+    products on G's device.  Returns (L, list of the inverted diagonal blocks)."""
+    import torch
+
+    n = G.shape[0]
+    A = G.clone()
+    L = torch.zeros_like(G)
+    inv_blocks = []
+    for j0 in range(0, n, block):
+        j1 = min(n, j0 + block)
+        d = A[j0:j1, j0:j1].cpu().numpy()
+        d = 0.5 * (d + d.conj().T)
+        Ljj = np.linalg.cholesky(d)
+        Linv = np.linalg.inv(Ljj)
+        Linv = np.tril(Linv)
+        Ljj_t = torch.from_numpy(Ljj).to(G.device)
+        Linv_t = torch.from_numpy(Linv).to(G.device)
+        inv_blocks.append(Linv_t)
+        L[j0:j1, j0:j1] = Ljj_t
+        if j1 < n:
+            X = A[j1:, j0:j1] @ Linv_t.conj().transpose(0, 1)      # panel L21 = A21 L11^-H
+            L[j1:, j0:j1] = X
+            A[j1:, j1:] -= X @ X.conj().transpose(0, 1)
+    return L, inv_blocks
+
+
+def _right_solve_upper(Z, L, inv_blocks, block: int = 512):
+    """Q with Q L^H = Z (L lower, so L^H is upper), by block columns:
+    Q_j = (Z_j - sum_{i<j} Q_i (L^H)_ij) (L_jj^H)^-1, all matrix products."""
+    import torch
+
+    n = L.shape[0]
+    Q = torch.empty_like(Z)
+    for b, j0 in enumerate(range(0, n, block)):
+        j1 = min(n, j0 + block)
+        rhs = Z[:, j0:j1]
+        if j0 > 0:
+            rhs = rhs - Q[:, :j0] @ L[j0:j1, :j0].conj().transpose(0, 1)
+        Q[:, j0:j1] = rhs @ inv_blocks[b].conj().transpose(0, 1)
+    return Q
+
+
+def cholesky_qr(Z, passes: int = 3):
+    """Orthonormal columns spanning those of the complex128 matrix Z (rows >=
+    columns): shifted Cholesky QR.  Each pass forms the Gram matrix G = Z^H Z,
+    its Cholesky factor G = L L^H and Z <- Z L^-H; the first pass factors
+    G + s I with s = 11 (m n + n (n + 1)) u ||Z||_2^2 (u the unit roundoff, the
+    2-norm bounded by the Frobenius norm) so that the factorisation exists
+    for any full-rank Z, the later passes restore orthonormality to rounding
+    level (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SIAM J. Sci.
+    Comput. 42 (2020), shifted CholeskyQR3).  The columns equal those of a
+    Householder QR up to a unit-modulus factor per column."""
+    import torch
+
+    m, n = Z.shape
+    if n > m:
+        raise ValueError("cholesky_qr needs at least as many rows as columns")
+    u = float(np.finfo(np.float64).eps) / 2.0
+    Q = Z
+    for p in range(passes):
+        G = Q.conj().transpose(0, 1) @ Q
+        G = 0.5 * (G + G.conj().transpose(0, 1))
+        if p == 0:
+            nrm2 = float((Q.real.square() + Q.imag.square()).sum().item())
+            s = 11.0 * (m * n + n * (n + 1)) * u * nrm2
+            G = G + s * torch.eye(n, dtype=G.dtype, device=G.device)
+        L, inv_blocks = _cholesky_lower(G)
+        Q = _right_solve_upper(Q, L, inv_blocks)
+    return Q
+
+
 def coulomb_diag(N: int) -> np.ndarray:
     I = np.arange(N, dtype=np.float64)
     return 4.0 * math.pi / (0.05 + (I / N) ** 2)
@@ -211,8 +289,7 @@ def generate_torch(shape: Shape | str, device, seed: Optional[int] = None, *,
         z = torch.empty_like(zraw)
         for c0 in range(0, nb_full, shape.n_b):
             c1 = min(nb_full, c0 + shape.n_b)
-            q, _ = torch.linalg.qr(zraw[:, c0:c1], mode="reduced")
-            z[:, c0:c1] = q
+            z[:, c0:c1] = cholesky_qr(zraw[:, c0:c1])
         zt = z[:, :nb].transpose(0, 1).contiguous().to(torch.complex64)
         del zraw, z
         acc = None

@@ -47,3 +47,43 @@ def test_omega_meshes():
     m16 = gwsynth.omega_mesh("m16")
     assert m13.size == 13 and m16.size == 16 and m13[0] == 0 and m16[0] == 0
     np.testing.assert_allclose([m16[1], m16[-1]], [0.01, 20.0])
+
+
+def test_device_orthonormalisation_matches_householder_up_to_phases():
+    """The torch backend's shifted Cholesky QR spans the same columns as a
+    LAPACK Householder QR: each column agrees up to a unit-modulus factor."""
+    import torch
+    rng = np.random.default_rng(5)
+    for m, n in ((300, 300), (700, 530), (90, 7)):
+        Z = gwsynth._cn(rng, (m, n))
+        Q = gwsynth.cholesky_qr(torch.from_numpy(Z)).numpy()
+        np.testing.assert_allclose(Q.conj().T @ Q, np.eye(n), atol=1e-13)
+        q, _ = np.linalg.qr(Z)
+        ph = np.sum(q.conj() * Q, axis=0)
+        np.testing.assert_allclose(np.abs(ph), 1.0, atol=1e-12)
+        np.testing.assert_allclose(Q, q * ph[None, :], atol=1e-12)
+
+
+def test_device_orthonormalisation_of_an_ill_conditioned_block():
+    """Condition number 1e7: the shifted first pass keeps the factorisation
+    defined and the later passes restore orthonormality."""
+    import torch
+    rng = np.random.default_rng(6)
+    m, n = 400, 200
+    a, _ = np.linalg.qr(gwsynth._cn(rng, (m, n)))
+    b, _ = np.linalg.qr(gwsynth._cn(rng, (n, n)))
+    Z = (a * np.geomspace(1.0, 1e-7, n)[None, :]) @ b
+    Q = gwsynth.cholesky_qr(torch.from_numpy(Z)).numpy()
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(n), atol=1e-12)
+    # same column space as Z
+    proj = Q @ (Q.conj().T @ Z)
+    assert np.linalg.norm(proj - Z) < 1e-10 * np.linalg.norm(Z)
+
+
+def test_torch_backend_on_the_host_is_deterministic():
+    import torch
+    s = gwsynth.make_shape(n_k=2, n_b=40, R=64, N=6, n_occ=2, n_unocc=50)   # 52 bands > 40: two QR blocks
+    a = gwsynth.generate_torch(s, torch.device("cpu"), seed=4)
+    b = gwsynth.generate_torch(s, torch.device("cpu"), seed=4)
+    assert torch.equal(a.psi, b.psi) and torch.equal(a.U, b.U) and np.array_equal(a.eps, b.eps)
+    assert a.psi.shape == (2, 52, 64) and a.psi.dtype == torch.complex64
