@@ -172,6 +172,21 @@ int gw_screen_workspace_size(int N, int n_omega, size_t* bytes_host);
 int gw_screen(void* stream, int N, int n_omega, const double* P, const double* v, double* W,
               int* info, void* ws, size_t ws_bytes);
 
+/* gw_screen_noalloc: gw_screen without a workspace, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  The sweep's panels live in a fixed
+ * array of gw_screen_noalloc_max_bytes() bytes (64 MiB) that the library holds
+ * on every GPU it runs on until the process ends; the call itself allocates
+ * nothing.  Arguments, results and info as for gw_screen.  A size whose
+ * panels exceed the array (gw_screen_workspace_size(N, n_omega) > the
+ * maximum, e.g. N > ~4000 at 16 frequencies) gives GW_ERR_WORKSPACE with
+ * nothing enqueued.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or threads without ordering) race and
+ * must be serialised by the caller.  Each call writes every panel element it
+ * reads, so no clearing is needed between calls. */
+size_t gw_screen_noalloc_max_bytes(void);
+int gw_screen_noalloc(void* stream, int N, int n_omega, const double* P, const double* v, double* W, int* info);
+
 
 /* ----------------------------------------------------------- learned high-band part
  * The unoccupied bands above a cutoff are left out of the explicit sum and

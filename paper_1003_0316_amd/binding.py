@@ -82,6 +82,9 @@ _lib.gw_polarization_workspace_size.argtypes = [ctypes.POINTER(GwPolDesc), ctype
 _lib.gw_polarization.argtypes = [_vp, ctypes.POINTER(GwPolDesc), _vp, _sz]
 _lib.gw_screen_workspace_size.argtypes = [_ci, _ci, ctypes.POINTER(_sz)]
 _lib.gw_screen.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp, _vp, _vp, _sz]
+_lib.gw_screen_noalloc.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp, _vp]
+_lib.gw_screen_noalloc_max_bytes.restype = _sz
+_lib.gw_screen_noalloc_max_bytes.argtypes = []
 
 class GwMlp(ctypes.Structure):
     _fields_ = [("n_in", ctypes.c_int), ("width", ctypes.c_int), ("n_out", ctypes.c_int),
@@ -126,6 +129,7 @@ _lib.gw_basis_select.argtypes = [_vp, _ci, _ci, _ci, _vp, _vp, ctypes.c_double, 
 
 EXPORTED = ("gw_last_error", "gw_version", "gw_project_workspace_size", "gw_project",
             "gw_polarization_workspace_size", "gw_polarization", "gw_screen_workspace_size", "gw_screen",
+            "gw_screen_noalloc_max_bytes", "gw_screen_noalloc",
             "gw_profile_enable", "gw_profile_reset", "gw_profile_query",
             "gw_mlp_sizes", "gw_mlp_sync_bf16", "gw_mlp_forward", "gw_mlp_loss", "gw_mlp_workspace_size",
             "gw_mlp_backward", "gw_mlp_adam_step", "gw_surrogate_workspace_size", "gw_surrogate_features",
@@ -328,6 +332,23 @@ def gw_screen(P: torch.Tensor, v: torch.Tensor, W: Optional[torch.Tensor] = None
     ws = workspace(nbytes, P.device, "screen")
     _check(_lib.gw_screen(_stream(stream), N, n_om, P.data_ptr(), v.data_ptr(), W.data_ptr(), info.data_ptr(),
                           ws.data_ptr(), ws.numel()))
+    return W, info
+
+
+def gw_screen_noalloc_max_bytes() -> int:
+    return int(_lib.gw_screen_noalloc_max_bytes())
+
+
+def gw_screen_noalloc(P: torch.Tensor, v: torch.Tensor, W: torch.Tensor, info: torch.Tensor, stream=None):
+    """gw_screen on the library's fixed scratch array (no workspace, no
+    allocation in the call): W and info must be given."""
+    _dev_tensor(P, "P", torch.complex128)
+    _dev_tensor(v, "v", torch.float64)
+    _dev_tensor(W, "W", torch.complex128)
+    _dev_tensor(info, "info", torch.int32)
+    n_om, N = P.shape[0], P.shape[1]
+    _check(_lib.gw_screen_noalloc(_stream(stream), N, n_om, P.data_ptr(), v.data_ptr(), W.data_ptr(),
+                                  info.data_ptr()))
     return W, info
 
 

@@ -271,3 +271,21 @@ def test_spectral_route_validation(b):
     d, keep = _desc(b, precision=3)                               # split FP16: at most 64 nodes
     _with_nodes(d, keep, np.linspace(0.2, 1.5, 65))
     assert _status(b, d) == -2
+
+
+def test_screen_noalloc_validation(b):
+    """The allocation-free screening rejects bad arguments and sizes whose
+    panels exceed its fixed array, before touching the device."""
+    L = b.lib()
+    fake = ctypes.c_void_p(0x7F0000003000)
+    other = ctypes.c_void_p(0x7F0000004000)
+    assert b.gw_screen_noalloc_max_bytes() == 64 << 20
+    assert L.gw_screen_noalloc(None, 0, 1, fake, fake, other, fake) == -1
+    assert L.gw_screen_noalloc(None, 4, 1, None, fake, other, fake) == -1
+    assert L.gw_screen_noalloc(None, 4, 1, fake, fake, fake, fake) == -1   # W aliases P
+    # largest N at 16 frequencies that fits, and the next size up that does not
+    fits = [N for N in range(64, 8193, 64) if b.gw_screen_workspace_size(N, 16) <= b.gw_screen_noalloc_max_bytes()]
+    too_big = max(fits) + 64
+    assert b.gw_screen_workspace_size(too_big, 16) > b.gw_screen_noalloc_max_bytes()
+    assert L.gw_screen_noalloc(None, too_big, 16, fake, fake, other, fake) == -3
+    assert "fixed array" in b.gw_last_error()
