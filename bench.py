@@ -628,9 +628,15 @@ def main() -> int:
         except FileNotFoundError as e:
             log(f"surrogate not applied: {e}")
 
+    learned = None
+    if surrogate is not None:
+        learned = surrogate.learned_call(U, psi, inp.eps, eps_dev, inp.omega, shp.n_occ, cutoff, inp.kq,
+                                         precision=a.precision, P=pol.P)
+        ws = torch.empty(learned.workspace_size(), dtype=torch.uint8, device=dev)
+
     def step():
-        if surrogate is not None:
-            _, rep = surrogate.run(pol, ws, U, psi, inp.eps, eps_dev, inp.omega, shp.n_occ, cutoff, inp.kq)
+        if learned is not None:
+            _, rep = learned.run(ws)
             sur_report.update(rep)
         else:
             pol.run(ws)

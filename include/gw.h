@@ -66,8 +66,23 @@ typedef enum gw_status {
   GW_ERR_INVALID_ARG = -1,  /* bad size, null pointer, non-insulating energies, w < 0 ... */
   GW_ERR_UNSUPPORTED = -2,  /* valid request the library does not implement */
   GW_ERR_WORKSPACE = -3,    /* workspace pointer null or smaller than required */
-  GW_ERR_HIP = -4           /* a HIP runtime call failed (message has the HIP error) */
+  GW_ERR_HIP = -4,          /* a HIP runtime call failed (message has the HIP error) */
+  GW_ERR_NONFINITE = -5,    /* GW_CHECK_FINITE: an input or a result holds Inf or NaN */
+  GW_ERR_NOT_HPD = -6       /* GW_CHECK_HPD: eps = 1 - sqrt(v) P sqrt(v) is not positive definite at some
+                               frequency (P is not negative semidefinite, Eqs. dielec_MB / screen_MB) */
 } gw_status;
+
+/* Optional checks (gw_pol_desc.flags, gw_screen_ex).  Each makes the call
+ * synchronise its stream, so a call with a check cannot be captured into a
+ * graph.
+ *   GW_CHECK_FINITE  the device inputs are scanned for Inf/NaN before any
+ *                    other work (nothing else is enqueued when one is found)
+ *                    and the results after the work; GW_ERR_NONFINITE names
+ *                    which.
+ *   GW_CHECK_HPD     gw_screen_ex: after the sweep, GW_ERR_NOT_HPD when a
+ *                    frequency's eps met a non-positive pivot (info still
+ *                    holds the failing column of every frequency). */
+enum { GW_CHECK_FINITE = 1, GW_CHECK_HPD = 2 };
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char* gw_last_error(void);
@@ -150,6 +165,7 @@ typedef struct gw_pol_desc {
   int real_inputs;          /* 1: U and psi are real float32 (see above); 0: complex */
   int n_nodes;              /* > 0: spectral route on these nodes (see above); 0: direct sum */
   const double* nodes_host; /* [n_nodes] transition-energy nodes (Hartree), increasing */
+  int flags;                /* 0 or GW_CHECK_FINITE (U, psi, eps before; P after) */
 } gw_pol_desc;
 
 int gw_polarization_workspace_size(const gw_pol_desc* desc_host, size_t* bytes_host);
@@ -171,6 +187,11 @@ int gw_polarization(void* stream, const gw_pol_desc* desc_host, void* ws, size_t
 int gw_screen_workspace_size(int N, int n_omega, size_t* bytes_host);
 int gw_screen(void* stream, int N, int n_omega, const double* P, const double* v, double* W,
               int* info, void* ws, size_t ws_bytes);
+/* gw_screen with checks: flags is 0 or a combination of GW_CHECK_FINITE (P
+ * and v before the sweep, W after it) and GW_CHECK_HPD (see above).  With
+ * flags = 0 it is gw_screen. */
+int gw_screen_ex(void* stream, int N, int n_omega, const double* P, const double* v, double* W, int* info,
+                 int flags, void* ws, size_t ws_bytes);
 
 /* gw_screen_noalloc: gw_screen without a workspace, for callers that cannot
  * allocate device memory (code under stream capture, tight serving loops,
@@ -269,6 +290,45 @@ int gw_surrogate_apply(void* stream, int N, int n_omega, const float* Y, int ldy
 int gw_surrogate_judge(void* stream, const gw_surr_desc* d_host, const float* Y, int ldy, const double* P_sample,
                        int n_sample, const int* sample_k_host, const int* sample_occ_host, double* err, void* ws,
                        size_t ws_bytes);
+
+/* ------------------------------------------------ learned path in one call
+ * gw_polarization_learned: P(i w_j) over all bands with the unoccupied bands
+ * above a cutoff replaced by the learned correction (the truncation that the
+ * paper's extrapolar approximation targets, Sec. "Test calculations",
+ * convergence with the number of bands), judged against an explicit sample
+ * and, when the judge fails, replaced by the explicit sum:
+ *   1. P_ret = gw_polarization over unoccupied bands [0, cut)
+ *   2. X = gw_surrogate_features(P_ret), Y = gw_mlp_forward(X)
+ *   3. judge (judge = 1): for n_sample_occ occupied bands of every k-set,
+ *      spread evenly from the lowest to the highest (the middle one when
+ *      n_sample_occ = 1), the left-out bands [cut, n_unocc) are projected
+ *      (Eq. proj_MB) and their exact left-out trace sum_t |w_t| |M_t|^2 taken;
+ *      err_j = |TR_sample,j / f_j - TR_pred,j| / TR_pred,j as for
+ *      gw_surrogate_judge.  err is copied to the host (the one stream
+ *      synchronisation of the call).
+ *   4. if every err_j <= judge_tol: P = P_ret + D P_ret D (gw_surrogate_apply)
+ *      else (fallback): the explicit sum over [cut, n_unocc) is added, so P is
+ *      the all-band result of gw_polarization.
+ * desc: as for gw_polarization over all bands: occ [0, n_occ), unocc [0,
+ * n_unocc), k_list_host NULL, accumulate 0, n_nodes 0, real_inputs 0,
+ * n_k <= 64; flags as there.  P is overwritten.  judge = 0 skips step 3 and
+ * always applies the correction; the call is then asynchronous.
+ * Workspace from gw_polarization_learned_workspace_size (the polarization
+ * passes', the perceptron's activations and the judge's projections). */
+typedef struct gw_learned_desc {
+  const gw_mlp* mlp;        /* trained perceptron (host struct of device pointers; inference reads wt) */
+  int cut;                  /* unoccupied bands summed explicitly, 1 <= cut < n_unocc */
+  int judge;                /* 1: judge and fall back; 0: apply without judging */
+  int n_sample_occ;         /* judge sample per k-set, 1 <= n_sample_occ <= n_occ, n_k * n_sample_occ <= 64 */
+  double judge_tol;         /* largest accepted err_j (finite, >= 0) */
+  double* judge_err_host;   /* optional host [n_omega] output: err_j (judge = 1) */
+  int* used_fallback_host;  /* optional host output: 1 when the explicit sum replaced the correction */
+} gw_learned_desc;
+
+int gw_polarization_learned_workspace_size(const gw_pol_desc* desc_host, const gw_learned_desc* learned_host,
+                                           size_t* bytes_host);
+int gw_polarization_learned(void* stream, const gw_pol_desc* desc_host, const gw_learned_desc* learned_host,
+                            void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------ basis optimization (v_min)
  * Sec. "Optimization of the MPB": only the Coulomb eigenfunctions with

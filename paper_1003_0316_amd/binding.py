@@ -26,7 +26,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 GW_FP64, GW_FP32, GW_SPLIT_BF16, GW_SPLIT_FP16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "split_bf16": GW_SPLIT_BF16, "split_fp16": GW_SPLIT_FP16}
 STATUS = {0: "GW_OK", -1: "GW_ERR_INVALID_ARG", -2: "GW_ERR_UNSUPPORTED", -3: "GW_ERR_WORKSPACE",
-          -4: "GW_ERR_HIP"}
+          -4: "GW_ERR_HIP", -5: "GW_ERR_NONFINITE", -6: "GW_ERR_NOT_HPD"}
+GW_CHECK_FINITE, GW_CHECK_HPD = 1, 2
 
 
 class GwError(RuntimeError):
@@ -52,6 +53,7 @@ class GwPolDesc(ctypes.Structure):
         ("accumulate", ctypes.c_int), ("chunk_pairs", ctypes.c_int),
         ("real_inputs", ctypes.c_int),
         ("n_nodes", ctypes.c_int), ("nodes_host", ctypes.POINTER(ctypes.c_double)),
+        ("flags", ctypes.c_int),
     ]
 
 
@@ -82,6 +84,7 @@ _lib.gw_polarization_workspace_size.argtypes = [ctypes.POINTER(GwPolDesc), ctype
 _lib.gw_polarization.argtypes = [_vp, ctypes.POINTER(GwPolDesc), _vp, _sz]
 _lib.gw_screen_workspace_size.argtypes = [_ci, _ci, ctypes.POINTER(_sz)]
 _lib.gw_screen.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp, _vp, _vp, _sz]
+_lib.gw_screen_ex.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp, _vp, _ci, _vp, _sz]
 _lib.gw_screen_noalloc.argtypes = [_vp, _ci, _ci, _vp, _vp, _vp, _vp]
 _lib.gw_screen_noalloc_max_bytes.restype = _sz
 _lib.gw_screen_noalloc_max_bytes.argtypes = []
@@ -97,6 +100,12 @@ class GwSurrDesc(ctypes.Structure):
                 ("n_k", ctypes.c_int), ("n_occ", ctypes.c_int), ("n_unocc", ctypes.c_int), ("cut", ctypes.c_int),
                 ("kq_host", ctypes.POINTER(ctypes.c_int)), ("eps", ctypes.c_void_p), ("P_ret", ctypes.c_void_p),
                 ("n_in", ctypes.c_int)]
+
+
+class GwLearnedDesc(ctypes.Structure):
+    _fields_ = [("mlp", ctypes.POINTER(GwMlp)), ("cut", ctypes.c_int), ("judge", ctypes.c_int),
+                ("n_sample_occ", ctypes.c_int), ("judge_tol", ctypes.c_double),
+                ("judge_err_host", ctypes.POINTER(ctypes.c_double)), ("used_fallback_host", ctypes.POINTER(ctypes.c_int))]
 
 
 _pm = ctypes.POINTER(GwMlp)
@@ -116,6 +125,10 @@ _lib.gw_surrogate_apply.argtypes = [_vp, _ci, _ci, _vp, _ci, _vp]
 _lib.gw_surrogate_judge.argtypes = [_vp, _ps, _vp, _ci, _vp, _ci, ctypes.POINTER(_ci), ctypes.POINTER(_ci), _vp, _vp,
                                     _sz]
 
+_pl = ctypes.POINTER(GwLearnedDesc)
+_lib.gw_polarization_learned_workspace_size.argtypes = [ctypes.POINTER(GwPolDesc), _pl, ctypes.POINTER(_sz)]
+_lib.gw_polarization_learned.argtypes = [_vp, ctypes.POINTER(GwPolDesc), _pl, _vp, _sz]
+
 _lib.gw_set_tuning.argtypes = [ctypes.c_char_p, _ci]
 _lib.gw_profile_enable.argtypes = [_ci]
 _lib.gw_profile_reset.argtypes = []
@@ -129,7 +142,8 @@ _lib.gw_basis_select.argtypes = [_vp, _ci, _ci, _ci, _vp, _vp, ctypes.c_double, 
 
 EXPORTED = ("gw_last_error", "gw_version", "gw_project_workspace_size", "gw_project",
             "gw_polarization_workspace_size", "gw_polarization", "gw_screen_workspace_size", "gw_screen",
-            "gw_screen_noalloc_max_bytes", "gw_screen_noalloc",
+            "gw_screen_noalloc_max_bytes", "gw_screen_noalloc", "gw_screen_ex",
+            "gw_polarization_learned_workspace_size", "gw_polarization_learned",
             "gw_profile_enable", "gw_profile_reset", "gw_profile_query",
             "gw_mlp_sizes", "gw_mlp_sync_bf16", "gw_mlp_forward", "gw_mlp_loss", "gw_mlp_workspace_size",
             "gw_mlp_backward", "gw_mlp_adam_step", "gw_surrogate_workspace_size", "gw_surrogate_features",
@@ -228,7 +242,7 @@ class PolarizationCall:
 
     def __init__(self, U, psi, eps_host, omega, n_occ, *, precision="fp64", eps_dev=None, P=None,
                  k_list=None, kq=None, occ_range=None, unocc_range=None, accumulate=False, chunk_pairs=0,
-                 real=False, nodes=None):
+                 real=False, nodes=None, flags=0):
         prec = _prec(precision)
         dt = torch.float32 if real else _cdtype(prec)
         _dev_tensor(U, "U", dt)
@@ -283,6 +297,7 @@ class PolarizationCall:
         else:
             d.n_nodes = 0
             d.nodes_host = None
+        d.flags = int(flags)
         self.desc = d
 
     def workspace_size(self) -> int:
@@ -311,15 +326,60 @@ def gw_polarization_workspace_size(U, psi, eps_host, omega, n_occ, **kw) -> int:
     return PolarizationCall(U, psi, eps_host, omega, n_occ, **kw).workspace_size()
 
 
+class LearnedCall:
+    """Marshalled arguments of one gw_polarization_learned call: the explicit
+    sum to the cutoff, the learned correction for the bands above it, the
+    judge and the fallback, in the library (see gw.h)."""
+
+    def __init__(self, pol: PolarizationCall, mlp, cut: int, *, judge: bool = True, n_sample_occ: int = 2,
+                 judge_tol: float = 0.25):
+        self.pol = pol
+        self.mlp = mlp
+        n_om = pol.desc.n_omega
+        self.err = np.zeros(n_om, dtype=np.float64)
+        self.fb = ctypes.c_int(0)
+        l = GwLearnedDesc()
+        l.mlp = ctypes.pointer(mlp.desc)
+        l.cut = int(cut)
+        l.judge = 1 if judge else 0
+        l.n_sample_occ = int(n_sample_occ)
+        l.judge_tol = float(judge_tol)
+        l.judge_err_host = self.err.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        l.used_fallback_host = ctypes.pointer(self.fb)
+        self.desc = l
+
+    def workspace_size(self) -> int:
+        out = _sz(0)
+        _check(_lib.gw_polarization_learned_workspace_size(ctypes.byref(self.pol.desc), ctypes.byref(self.desc),
+                                                           ctypes.byref(out)))
+        return out.value
+
+    def run(self, ws: Optional[torch.Tensor] = None, stream=None):
+        """Returns (P, report); report has judge_err (per frequency, judged
+        calls) and used_fallback."""
+        nbytes = self.workspace_size()
+        if ws is None:
+            ws = workspace(nbytes, self.pol.P.device, "learned")
+        _check(_lib.gw_polarization_learned(_stream(stream), ctypes.byref(self.pol.desc), ctypes.byref(self.desc),
+                                            ws.data_ptr(), ws.numel()))
+        rep = {"used_fallback": bool(self.fb.value)}
+        if self.desc.judge:
+            rep["judge_err"] = self.err.tolist()
+            rep["judge_err_max"] = float(self.err.max())
+        return self.pol.P, rep
+
+
 def gw_screen_workspace_size(N: int, n_omega: int) -> int:
     out = _sz(0)
     _check(_lib.gw_screen_workspace_size(N, n_omega, ctypes.byref(out)))
     return out.value
 
 
-def gw_screen(P: torch.Tensor, v: torch.Tensor, W: Optional[torch.Tensor] = None, info=None, stream=None):
+def gw_screen(P: torch.Tensor, v: torch.Tensor, W: Optional[torch.Tensor] = None, info=None, stream=None,
+              flags: int = 0):
     """W[j] = (1 - diag(v) P[j])^-1 diag(v) in FP64.  Returns (W, info) with
-    info an int32 device tensor (0 = ok, c+1 = pivot failure at column c)."""
+    info an int32 device tensor (0 = ok, c+1 = pivot failure at column c).
+    flags: GW_CHECK_FINITE / GW_CHECK_HPD (gw_screen_ex)."""
     _dev_tensor(P, "P", torch.complex128)
     _dev_tensor(v, "v", torch.float64)
     n_om, N = P.shape[0], P.shape[1]
@@ -330,8 +390,8 @@ def gw_screen(P: torch.Tensor, v: torch.Tensor, W: Optional[torch.Tensor] = None
         info = torch.empty(n_om, dtype=torch.int32, device=P.device)
     nbytes = gw_screen_workspace_size(N, n_om)
     ws = workspace(nbytes, P.device, "screen")
-    _check(_lib.gw_screen(_stream(stream), N, n_om, P.data_ptr(), v.data_ptr(), W.data_ptr(), info.data_ptr(),
-                          ws.data_ptr(), ws.numel()))
+    _check(_lib.gw_screen_ex(_stream(stream), N, n_om, P.data_ptr(), v.data_ptr(), W.data_ptr(), info.data_ptr(),
+                             int(flags), ws.data_ptr(), ws.numel()))
     return W, info
 
 

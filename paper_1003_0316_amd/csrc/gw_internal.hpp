@@ -110,6 +110,28 @@ int launch_herk_f64(hipStream_t s, int N, int T, const double2* M, long ldm, con
                     int n_omega, double2* P);
 int launch_hermitian_mirror(hipStream_t s, int N, int n_omega, double2* P);
 
+// ---- finite checks (k_fp64.hip) ---------------------------------------------
+constexpr size_t kFlagBytes = 256;  // one device flag at the end of a workspace
+int launch_flag_clear(hipStream_t s, unsigned* flag);
+// flag |= 1 if any of n_values floats (or doubles when f64) is Inf or NaN.
+int launch_nonfinite(hipStream_t s, const void* p, size_t n_values, bool f64, unsigned* flag);
+// Copies the flag to the host and synchronises the stream.
+int read_flag(hipStream_t s, const unsigned* flag, unsigned* host);
+
+// ---- learned correction (k_surrogate.hip) ------------------------------------
+// Partial sums per sample row of launch_sample_trace, per frequency.
+int sample_trace_parts(int N, int nu);
+// Left-out trace partials of one judge sample row from its projections M
+// [N][ldm] (c128 or c64), columns t < nu with energies eu[t], occupied energy
+// *eo: part[p][j] for p < sample_trace_parts(N, nu).
+int launch_sample_trace(hipStream_t s, bool c128, const void* M, int N, int nu, long ldm, const double* eo,
+                        const double* eu, const OmegaList& om, double* part);
+// err[j] from the predicted left-out trace (P_ret, Y) and the sample's traces
+// (n_part partials per frequency, summed in order), scaled by the sample rows'
+// share of the left-out weight sum.  ws: gw_surrogate_workspace_size bytes.
+int surrogate_judge_traces(hipStream_t s, const gw_surr_desc& d, const float* Y, int ldy, const double* part,
+                           int n_part, int n_rows, const int* rk, const int* ro, double* err, void* ws);
+
 // ---- screening (k_screen.hip) ---------------------------------------------------
 size_t screen_workspace_bytes(int N, int n_omega);
 int screen_run(hipStream_t s, int N, int n_omega, const double2* P, const double* v, double2* W,

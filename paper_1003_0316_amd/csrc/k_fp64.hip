@@ -266,6 +266,51 @@ int launch_hermitian_mirror(hipStream_t s, int N, int n_omega, double2* P) {
 }
 
 
+// ---- finite checks ------------------------------------------------------------
+namespace {
+__global__ void flag_clear_kernel(unsigned* __restrict__ flag) {
+  if (threadIdx.x == 0) flag[0] = 0u;
+}
+
+// flag |= 1 if any of the n values (IEEE float, or double when f64) has an
+// all-ones exponent (Inf or NaN).  For doubles only the high word is read.
+__global__ __launch_bounds__(256) void nonfinite_kernel(const uint32_t* __restrict__ w, size_t n, int f64,
+                                                        unsigned* __restrict__ flag) {
+  unsigned bad = 0u;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    if (f64) {
+      const uint32_t hi = w[2 * i + 1];
+      bad |= (hi & 0x7ff00000u) == 0x7ff00000u;
+    } else {
+      bad |= (w[i] & 0x7f800000u) == 0x7f800000u;
+    }
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+}  // namespace
+
+int launch_flag_clear(hipStream_t s, unsigned* flag) {
+  hipLaunchKernelGGL(flag_clear_kernel, dim3(1), dim3(64), 0, s, flag);
+  GW_LAUNCHED("flag_clear_kernel");
+  return GW_OK;
+}
+
+int launch_nonfinite(hipStream_t s, const void* p, size_t n_values, bool f64, unsigned* flag) {
+  if (n_values == 0) return GW_OK;
+  const unsigned blocks = (unsigned)std::min<size_t>((n_values + 255) / 256, 8192);
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const uint32_t*>(p), n_values,
+                     f64 ? 1 : 0, flag);
+  GW_LAUNCHED("nonfinite_kernel");
+  return GW_OK;
+}
+
+int read_flag(hipStream_t s, const unsigned* flag, unsigned* host) {
+  GW_HIP(hipMemcpyAsync(host, flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  GW_HIP(hipStreamSynchronize(s));
+  return GW_OK;
+}
+
+
 namespace {
 struct FreqList {
   int n;

@@ -19,6 +19,7 @@ namespace {
 constexpr int kMaxK = 64;
 constexpr int kMaxRows = 64;
 constexpr int NF = 12;  // features used (rest of the row is zero)
+inline int cdiv_int(long a, long b) { return (int)((a + b - 1) / b); }
 
 struct KMap {
   int n_k;
@@ -208,6 +209,73 @@ __global__ __launch_bounds__(256) void judge_kernel(int N, const float* __restri
   }
 }
 
+// Left-out trace of one judge sample row (k, n) from its projections M
+// [N][ldm] (columns t < nu: the unoccupied bands cut.. of set kq):
+//   TR_j = sum_I |Re P_II| = sum_t |w_t(j)| sum_I |M_It|^2,
+// since every w_t(j) = 4 D_t / (D_t^2 + w_j^2) < 0.  Block (x, y) covers
+// columns 256 x .. and rows 256 y ..; its partial sums per frequency go to
+// part[(y * gridDim.x + x) * n_omega + j] (fixed-order tree in LDS).
+template <class CT>
+__global__ __launch_bounds__(256) void sample_trace_kernel(const CT* __restrict__ M, int N, int nu, long ldm,
+                                                           const double* __restrict__ eo,
+                                                           const double* __restrict__ eu, OmegaList om,
+                                                           double* __restrict__ part) {
+  __shared__ double red[256];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int i0 = blockIdx.y * 256, i1 = min(N, i0 + 256);
+  double c = 0.0;
+  if (t < nu)
+    for (int I = i0; I < i1; ++I) {
+      const CT m = M[(size_t)I * ldm + t];
+      c += (double)m.x * (double)m.x + (double)m.y * (double)m.y;
+    }
+  const double d = t < nu ? eo[0] - eu[t] : -1.0;
+  double* out = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * om.n;
+  for (int j = 0; j < om.n; ++j) {
+    red[threadIdx.x] = t < nu ? c * fabs(4.0 * d / (d * d + om.w[j] * om.w[j])) : 0.0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+    __syncthreads();
+  }
+}
+
+// trs[j] = sum over p < n_part of part[p * n_om + j], in order.
+__global__ void trace_final_kernel(int n_part, int n_om, const double* __restrict__ part, double* __restrict__ trs) {
+  const int j = threadIdx.x;
+  if (j >= n_om) return;
+  double s = 0.0;
+  for (int p = 0; p < n_part; ++p) s += part[(size_t)p * n_om + j];
+  trs[j] = s;
+}
+
+// Judge from the sample's left-out trace trs (see judge_kernel).
+__global__ __launch_bounds__(256) void judge_tr_kernel(int N, const float* __restrict__ Y, int ldy,
+                                                       const double2* __restrict__ Pr,
+                                                       const double* __restrict__ trs,
+                                                       const double* __restrict__ all_sums,
+                                                       const double* __restrict__ sample_sums,
+                                                       double* __restrict__ err) {
+  __shared__ double ra[256];
+  const int j = blockIdx.x;
+  const double2* Prj = Pr + (size_t)j * N * N;
+  double tp = 0.0;
+  for (int i = threadIdx.x; i < N; i += 256) tp += fabs(Prj[(size_t)i * N + i].x) * exp(yclamp(Y[((size_t)j * N + i) * ldy]));
+  ra[threadIdx.x] = tp;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) ra[threadIdx.x] += ra[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double f = sample_sums[2 * j + 1] / all_sums[2 * j + 1];
+    err[j] = fabs(trs[j] / f - ra[0]) / fmax(ra[0], 1e-300);
+  }
+}
+
 int fill_kmap(int n_k, const int* kq_host, KMap& km) {
   if (n_k > kMaxK) return fail(GW_ERR_UNSUPPORTED, "surrogate: at most 64 k-sets");
   km.n_k = n_k;
@@ -250,6 +318,53 @@ int run_wsum(hipStream_t s, const gw_surr_desc& d, const KMap& km, const RowList
 }
 
 }  // namespace
+
+int sample_trace_parts(int N, int nu) { return cdiv_int(N, 256) * cdiv_int(nu, 256); }
+
+int launch_sample_trace(hipStream_t s, bool c128, const void* M, int N, int nu, long ldm, const double* eo,
+                        const double* eu, const OmegaList& om, double* part) {
+  dim3 grid(cdiv_int(nu, 256), cdiv_int(N, 256));
+  if (c128)
+    hipLaunchKernelGGL(sample_trace_kernel<double2>, grid, dim3(256), 0, s, static_cast<const double2*>(M), N, nu,
+                       ldm, eo, eu, om, part);
+  else
+    hipLaunchKernelGGL(sample_trace_kernel<float2>, grid, dim3(256), 0, s, static_cast<const float2*>(M), N, nu,
+                       ldm, eo, eu, om, part);
+  GW_LAUNCHED("sample_trace_kernel");
+  return GW_OK;
+}
+
+int surrogate_judge_traces(hipStream_t s, const gw_surr_desc& d, const float* Y, int ldy, const double* part,
+                           int n_part, int n_rows, const int* rk, const int* ro, double* err, void* ws) {
+  OmegaList om;
+  KMap km;
+  int st;
+  if ((st = fill_omega(d.n_omega, d.omega_host, om)) != GW_OK) return st;
+  if ((st = fill_kmap(d.n_k, d.kq_host, km)) != GW_OK) return st;
+  if (n_rows < 1 || n_rows > kMaxRows) return fail(GW_ERR_INVALID_ARG, "judge: 1..64 sample rows");
+  RowList rl;
+  rl.n = n_rows;
+  for (int i = 0; i < kMaxRows; ++i) {
+    rl.k[i] = i < n_rows ? rk[i] : 0;
+    rl.o[i] = i < n_rows ? ro[i] : 0;
+  }
+  Carver cv(ws);
+  double* wpart = cv.take<double>((size_t)std::max(d.n_k * d.n_occ, kMaxRows) * d.n_omega * 2);
+  double* sums = cv.take<double>(2 * kMaxOmega);
+  double* ssum = cv.take<double>(2 * kMaxOmega);
+  double* trs = cv.take<double>(2 * kMaxOmega);
+  RowList all;
+  all.n = 0;
+  if ((st = run_wsum(s, d, km, all, om, wpart, sums)) != GW_OK) return st;
+  if ((st = run_wsum(s, d, km, rl, om, wpart, ssum)) != GW_OK) return st;
+  hipLaunchKernelGGL(trace_final_kernel, dim3(1), dim3(64), 0, s, n_part, d.n_omega, part, trs);
+  GW_LAUNCHED("trace_final_kernel");
+  hipLaunchKernelGGL(judge_tr_kernel, dim3(d.n_omega), dim3(256), 0, s, d.N, Y, ldy,
+                     reinterpret_cast<const double2*>(d.P_ret), trs, sums, ssum, err);
+  GW_LAUNCHED("judge_tr_kernel");
+  return GW_OK;
+}
+
 }  // namespace gw
 
 using namespace gw;

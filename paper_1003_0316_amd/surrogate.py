@@ -1,16 +1,16 @@
-"""Learned correction for the unoccupied bands above a cutoff (host-side
-orchestration of the library's kernels; every arithmetic step runs on the GPU).
-
-Path (one q-point):
-  1. P_ret  = gw_polarization over unoccupied bands [0, cut)
-  2. X      = gw_surrogate_features(P_ret, band energies, frequencies)
-  3. Y      = gw_mlp_forward(X)           (column 0: y = log(d_I / |P_ret,II|))
-  4. judge  = the left-out bands [cut, n_unocc) summed explicitly for a sample
-              of occupied rows; gw_surrogate_judge compares the predicted and the
-              sampled left-out trace
-  5. P      = P_ret + D P_ret D (gw_surrogate_apply) if the judge passes,
-              otherwise the explicit sum over the left-out bands is added
-              (fallback; P is then the full-band result).
+"""Learned correction for the unoccupied bands above a cutoff: loading the
+trained perceptron and marshalling the library's learned polarization call.
+Every arithmetic step runs in libgw (gw_polarization_learned):
+  1. P_ret  = the explicit sum over unoccupied bands [0, cut)
+  2. X      = features of P_ret, band energies, frequencies;  Y = perceptron(X)
+             (column 0: y = log(d_I / |P_ret,II|))
+  3. judge  = the left-out bands [cut, n_unocc) projected explicitly for a
+              sample of occupied bands spread over the occupied range; the
+              predicted and the sampled left-out trace are compared
+  4. P      = P_ret + D P_ret D if the judge passes, otherwise the explicit
+              sum over the left-out bands is added (fallback; P is then the
+              full-band result).
+predict() and apply() expose steps 2 and 4 alone (training, ablations).
 """
 from __future__ import annotations
 
@@ -79,32 +79,11 @@ class Surrogate:
         gw.gw_surrogate_apply(P, Y, self.mlp.n_out)
         return Y
 
-    def run(self, pol: gw.PolarizationCall, ws: torch.Tensor, U, psi, eps_host, eps_dev, omega, n_occ: int,
-            cut: int, kq=None, sample_occ: int = 2, judge: bool = True):
-        """Steps 1-5 for the polarization call `pol` (already set up for the
-        bands [0, cut)).  Returns (P, report)."""
-        P = pol.run(ws)
-        n_unocc = eps_host.shape[1] - n_occ
-        report = {"judge_err_max": None, "used_fallback": False}
-        Y, args = self.predict(P, eps_dev, omega, n_occ, cut, kq)
-        if judge and cut < n_unocc:
-            n_k = eps_host.shape[0]
-            Ps = self._tensor("P_sample", tuple(P.shape), torch.complex128, P.device)
-            samp = gw.PolarizationCall(U, psi, eps_host, omega, n_occ, precision=pol.desc.precision,
-                                       eps_dev=eps_dev, P=Ps, kq=kq, occ_range=(0, sample_occ),
-                                       unocc_range=(cut, n_unocc))
-            samp.run()
-            rows = [(k, n) for k in range(n_k) for n in range(sample_occ)]
-            err = gw.gw_surrogate_judge(args, Y, self.mlp.n_out, Ps, rows)
-            e = err.cpu().numpy()
-            report["judge_err_max"] = float(e.max())
-            report["judge_err"] = e.tolist()
-            if not (e.max() <= self.judge_tol):
-                report["used_fallback"] = True
-                full = gw.PolarizationCall(U, psi, eps_host, omega, n_occ, precision=pol.desc.precision,
-                                           eps_dev=eps_dev, P=P, kq=kq, unocc_range=(cut, n_unocc),
-                                           accumulate=True)
-                full.run()
-                return P, report
-        gw.gw_surrogate_apply(P, Y, self.mlp.n_out)
-        return P, report
+    def learned_call(self, U, psi, eps_host, eps_dev, omega, n_occ: int, cut: int, kq=None, *,
+                     precision="split_bf16", P=None, n_sample_occ: int = 2, judge: bool = True,
+                     flags: int = 0) -> gw.LearnedCall:
+        """The marshalled library call for P over all bands with the bands
+        above `cut` replaced by the correction (judged, with fallback)."""
+        pol = gw.PolarizationCall(U, psi, eps_host, omega, n_occ, precision=precision, eps_dev=eps_dev, P=P, kq=kq,
+                                  flags=flags)
+        return gw.LearnedCall(pol, self.mlp, cut, judge=judge, n_sample_occ=n_sample_occ, judge_tol=self.judge_tol)

@@ -289,3 +289,68 @@ def test_screen_noalloc_validation(b):
     assert b.gw_screen_workspace_size(too_big, 16) > b.gw_screen_noalloc_max_bytes()
     assert L.gw_screen_noalloc(None, too_big, 16, fake, fake, other, fake) == -3
     assert "fixed array" in b.gw_last_error()
+
+
+def _learned(b, d, keep, **kw):
+    m = b.GwMlp(32, 256, 32, 0x7F0000005000, None, None, 0x7F0000006000, 0x7F0000007000)
+    keep["mlp"] = m
+    l = b.GwLearnedDesc()
+    l.mlp = ctypes.pointer(m)
+    l.cut, l.judge, l.n_sample_occ, l.judge_tol = 2, 1, 1, 0.25
+    for k, v in kw.items():
+        setattr(l, k, v)
+    return l
+
+
+def _lstatus(b, d, l):
+    out = ctypes.c_size_t(0)
+    return b.lib().gw_polarization_learned_workspace_size(ctypes.byref(d), ctypes.byref(l), ctypes.byref(out))
+
+
+def test_learned_call_validation(b):
+    """gw_polarization_learned rejects, before any launch: a missing
+    perceptron, a cutoff outside [1, n_unocc), partial band ranges, k lists,
+    accumulation and the spectral route, bad sample counts and tolerances."""
+    d, keep = _desc(b, n_unocc=5)
+    assert _lstatus(b, d, _learned(b, d, keep)) == 0
+    L = b.lib()
+    out = ctypes.c_size_t(0)
+    assert L.gw_polarization_learned_workspace_size(ctypes.byref(d), None, ctypes.byref(out)) == -1
+    for kw in ({"cut": 0}, {"cut": 5}, {"n_sample_occ": 0}, {"n_sample_occ": 3}, {"judge_tol": -1.0},
+               {"judge_tol": float("nan")}, {"judge": 2}):
+        assert _lstatus(b, d, _learned(b, d, keep, **kw)) == -1, kw
+    l = _learned(b, d, keep)
+    l.mlp.contents.n_in = 12
+    assert _lstatus(b, d, l) == -1
+    d2, keep2 = _desc(b, n_unocc=5)
+    d2.unocc_end = 4
+    assert _lstatus(b, d2, _learned(b, d2, keep2)) == -1
+    d3, keep3 = _desc(b, n_unocc=5)
+    d3.accumulate = 1
+    assert _lstatus(b, d3, _learned(b, d3, keep3)) == -2
+    d4, keep4 = _desc(b, n_unocc=5)
+    keep4["kl"] = np.array([0], dtype=np.int32)
+    d4.k_list_host = keep4["kl"].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    d4.n_k_list = 1
+    assert _lstatus(b, d4, _learned(b, d4, keep4)) == -2
+    # judge = 0 needs no sample
+    assert _lstatus(b, d, _learned(b, d, keep, judge=0, n_sample_occ=0)) == 0
+    # a valid call with too small a workspace
+    l = _learned(b, d, keep)
+    need = ctypes.c_size_t(0)
+    assert L.gw_polarization_learned_workspace_size(ctypes.byref(d), ctypes.byref(l), ctypes.byref(need)) == 0
+    assert L.gw_polarization_learned(None, ctypes.byref(d), ctypes.byref(l), ctypes.c_void_p(0x7F0000008000),
+                                     need.value - 1) == -3
+
+
+def test_check_flags_validation(b):
+    d, keep = _desc(b)
+    d.flags = 4
+    out = ctypes.c_size_t(0)
+    assert b.lib().gw_polarization(None, ctypes.byref(d), ctypes.c_void_p(0x7F0000008000), 1 << 40) == -1
+    L = b.lib()
+    fake = ctypes.c_void_p(0x7F0000003000)
+    other = ctypes.c_void_p(0x7F0000004000)
+    assert L.gw_screen_ex(None, 4, 1, fake, fake, other, fake, 8, fake, 1 << 30) == -1
+    assert "unknown flags" in b.gw_last_error()
+    assert b.STATUS[-5] == "GW_ERR_NONFINITE" and b.STATUS[-6] == "GW_ERR_NOT_HPD"

@@ -11,7 +11,7 @@ from paper_1003_0316_amd import binding as b
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PAIRS = [("gw_pol_desc", b.GwPolDesc), ("gw_sigma_desc", b.GwSigmaDesc), ("gw_mlp", b.GwMlp),
-         ("gw_surr_desc", b.GwSurrDesc)]
+         ("gw_surr_desc", b.GwSurrDesc), ("gw_learned_desc", b.GwLearnedDesc)]
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="needs a host C compiler")

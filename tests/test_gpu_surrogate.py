@@ -240,10 +240,7 @@ def test_surrogate_judge_forces_fallback(lib):
     psi = torch.from_numpy(inp.psi).to(dev, torch.complex64)
     eps = torch.from_numpy(inp.eps).to(dev)
     sur = Surrogate.load_default(dev, judge_tol=0.0)
-    pol = lib.PolarizationCall(U, psi, inp.eps, inp.omega, 3, precision="split_bf16", eps_dev=eps, kq=inp.kq,
-                               unocc_range=(0, 20))
-    ws = torch.empty(pol.workspace_size(), dtype=torch.uint8, device=dev)
-    P, rep = sur.run(pol, ws, U, psi, inp.eps, eps, inp.omega, 3, 20, inp.kq)
+    P, rep = sur.learned_call(U, psi, inp.eps, eps, inp.omega, 3, 20, inp.kq, precision="split_bf16").run()
     torch.cuda.synchronize()
     assert rep["used_fallback"]
     Ur = inp.U.astype(np.complex64).astype(np.complex128)
