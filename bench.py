@@ -43,12 +43,18 @@ def log(msg: str) -> None:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c2"])
+    ap.add_argument("--workload", default="c5", choices=["c5", "c4", "c3", "c2"])
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "split_fp16", "fp32"])
     ap.add_argument("--cutoff", type=int, default=None, help="explicit unoccupied bands (default: workload's)")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain-path comparison")
+    ap.add_argument("--fp32-full", action="store_true",
+                    help="time the FP32 plain path over every pair of the q-point instead of a sample")
+    ap.add_argument("--no-model-error", action="store_true",
+                    help="skip the all-band reference pass (model error of the learned correction)")
+    ap.add_argument("--sample-occ", type=int, default=2, help="judge sample: occupied bands per k-point")
+    ap.add_argument("--judge-tol", type=float, default=0.25, help="judge tolerance of the learned correction")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time for cpu_baseline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -80,8 +86,9 @@ def parse():
     ap.add_argument("--ablation-seeds", type=int, default=4, help="held-out seeds for --surrogate-ablation")
     ap.add_argument("--tuning", action="append", default=[], metavar="KEY=VALUE",
                     help="kernel selection switch passed to gw_set_tuning before the run (repeatable)")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_c5.json"),
-                    help="measured per-launch HBM traffic of the dominant kernel (from rocprofv3 --pmc)")
+    ap.add_argument("--traffic", default=None,
+                    help="measured per-launch HBM traffic of the dominant kernel (from rocprofv3 --pmc; default "
+                         "profiles/traffic_<workload>.json)")
     return ap.parse_args()
 
 
@@ -547,7 +554,7 @@ def summarize_pmc(a) -> int:
         out["symbol"] = dom
         out["bytes_per_launch"] = out["kernels"][dom]["fetch_bytes_per_launch"] + \
             out["kernels"][dom]["write_bytes_per_launch"]
-    with open(a.traffic, "w") as fh:
+    with open(a.traffic or os.path.join(ROOT, "profiles", f"traffic_{a.workload}.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
     return 0
@@ -560,6 +567,56 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_1003_0316_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def _pairs_and_flops(shp, cutoff, n_om, sample_rows, fallback):
+    """Algorithmic flops of one step: projection 8 N R per pair, Hermitian
+    accumulation 4 N (N + 1) per pair and frequency, FP64 screening N^3 / 2
+    complex multiply-adds per frequency; the judge's sample pairs are projected
+    only."""
+    N = shp.N
+    T_main = shp.n_k * shp.n_occ * cutoff
+    if fallback:
+        T_main += shp.n_k * shp.n_occ * (shp.n_unocc - cutoff)
+    T_sample = sample_rows * (shp.n_unocc - cutoff) if cutoff < shp.n_unocc else 0
+    return T_main, T_sample, {
+        "proj": 8.0 * N * shp.R * T_main, "acc": 4.0 * N * (N + 1) * T_main * n_om,
+        "sample": 8.0 * N * shp.R * T_sample, "screen": 0.5 * N ** 3 * 8.0 * n_om}
+
+
+def _block(P, S):
+    """P[:, S][:, :, S] as a host array (S a device index tensor)."""
+    return P[:, S][:, :, S].cpu().numpy()
+
+
+def _rel_per_omega(x, ref):
+    """Relative Frobenius error per frequency of device arrays [n_om][..]."""
+    import torch
+    d = torch.linalg.vector_norm((x - ref).reshape(x.shape[0], -1), dim=1)
+    r = torch.linalg.vector_norm(ref.reshape(ref.shape[0], -1), dim=1)
+    return (d / r).cpu().numpy()
+
+
+def _w_residual(P, W, v, S):
+    """Per frequency ||W[S,:] - diag(v_S) P[S,:] W - diag(v)[S,:]||_F / ||v_S||:
+    the sampled rows of (1 - vP) W = v (Eq. W_Dyson in matrix form)."""
+    import torch
+    out = []
+    vs = v[S]
+    for j in range(P.shape[0]):
+        lhs = W[j][S] - vs[:, None] * (P[j][S].contiguous() @ W[j])
+        lhs[torch.arange(S.numel(), device=S.device), S] -= vs
+        out.append(float(torch.linalg.vector_norm(lhs) / torch.linalg.vector_norm(vs)))
+    return out
+
+
+def _diag_view(d):
+    """A [n_om][N][N] read-only view whose (j, i, i) element is d[j, i] (no
+    N x N storage): the oracle's feature function reads only the diagonal."""
+    import numpy as np
+    d = np.ascontiguousarray(d)
+    return np.lib.stride_tricks.as_strided(d, shape=(d.shape[0], d.shape[1], d.shape[1]),
+                                           strides=(d.strides[0], d.strides[1], 0), writeable=False)
 
 
 def main() -> int:
@@ -597,10 +654,18 @@ def main() -> int:
     import gwsynth
     from paper_1003_0316_amd import binding as gw
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     shp = gwsynth.SHAPES[a.workload]
     cutoff = a.cutoff or shp.n_unocc_cut or shp.n_unocc
+    learned_path = cutoff < shp.n_unocc
+    surrogate = None
+    if learned_path:
+        from paper_1003_0316_amd import surrogate as sg
+        if not os.path.exists(sg.DEFAULT_MODEL):
+            print(f"bench.py: workload {a.workload} cuts the band sum at {cutoff} and needs the trained model "
+                  f"{sg.DEFAULT_MODEL}, which is missing (no silent truncation)", file=sys.stderr)
+            return 2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     log(f"workload {a.workload}: N_k={shp.n_k} N={shp.N} R={shp.R} occ={shp.n_occ} unocc={shp.n_unocc} "
         f"cutoff={cutoff} precision={a.precision}")
     t0 = time.time()
@@ -614,33 +679,32 @@ def main() -> int:
     N = shp.N
 
     # ------------------------------------------------------------------ the step
-    pol = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision=a.precision, eps_dev=eps_dev,
-                              kq=inp.kq, unocc_range=(0, cutoff))
-    ws = torch.empty(pol.workspace_size(), dtype=torch.uint8, device=dev)
-    W = torch.empty_like(pol.P)
+    W = torch.empty((n_om, N, N), dtype=torch.complex128, device=dev)
     info = torch.empty(n_om, dtype=torch.int32, device=dev)
-    surrogate = None
     sur_report = {}
-    if cutoff < shp.n_unocc:
-        from paper_1003_0316_amd import surrogate as sg
-        try:
-            surrogate = sg.Surrogate.load_default(dev)
-        except FileNotFoundError as e:
-            log(f"surrogate not applied: {e}")
-
-    learned = None
-    if surrogate is not None:
+    n_sample_occ = a.sample_occ
+    if learned_path:
+        surrogate = sg.Surrogate.load_default(dev, judge_tol=a.judge_tol)
         learned = surrogate.learned_call(U, psi, inp.eps, eps_dev, inp.omega, shp.n_occ, cutoff, inp.kq,
-                                         precision=a.precision, P=pol.P)
+                                         precision=a.precision, n_sample_occ=n_sample_occ)
+        P = learned.pol.P
         ws = torch.empty(learned.workspace_size(), dtype=torch.uint8, device=dev)
 
-    def step():
-        if learned is not None:
+        def run_p():
             _, rep = learned.run(ws)
             sur_report.update(rep)
-        else:
+    else:
+        pol = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision=a.precision, eps_dev=eps_dev,
+                                  kq=inp.kq, unocc_range=(0, cutoff))
+        P = pol.P
+        ws = torch.empty(pol.workspace_size(), dtype=torch.uint8, device=dev)
+
+        def run_p():
             pol.run(ws)
-        gw.gw_screen(pol.P, v_dev, W=W, info=info)
+
+    def step():
+        run_p()
+        gw.gw_screen(P, v_dev, W=W, info=info)
 
     for i in range(a.warmup):
         step()
@@ -660,27 +724,22 @@ def main() -> int:
     gw.gw_profile_enable(False)
     ms = e0.elapsed_time(e1) / a.steps
     log(f"timed {a.steps} step(s): {ms / 1e3:.3f} s/step (wall {wall:.1f} s)")
-    if int(info.abs().sum()) != 0:
-        log(f"WARNING: screening reported non-positive pivots: {info.cpu().numpy()}")
+    info_h = info.cpu().numpy()
+    screening_ok = bool(np.all(info_h == 0))
+    if not screening_ok:
+        log(f"ERROR: screening met non-positive pivots (eps not positive definite): info {info_h.tolist()}")
+    fallback = bool(sur_report.get("used_fallback", False))
 
     pre = "bf16" if a.precision == "split_bf16" else ("f16" if a.precision == "split_fp16" else "f32")
     kernels = {}
     for name in (f"project_{pre}_kernel", f"herk_{pre}_kernel", "pair_product_kernel", "scale_split_kernel",
-                 "update_kernel", "apply_kernel"):
+                 "update_kernel", "apply_kernel", "project_rows_bf16_kernel"):
         n, tot = gw.gw_profile_query(name)
         kernels[name] = {"launches": n, "total_ms": tot}
-    T_pairs = shp.n_k * shp.n_occ * cutoff
-    # pairs actually projected/accumulated in a step: the explicit sum, the
-    # judge's sample of left-out bands and (if the judge failed) the fallback
-    T_run = T_pairs
-    if surrogate is not None:
-        T_run += shp.n_k * 2 * (shp.n_unocc - cutoff)
-        if sur_report.get("used_fallback"):
-            T_run += shp.n_k * shp.n_occ * (shp.n_unocc - cutoff)
-    flops_proj = 8.0 * N * shp.R * T_run
-    flops_acc = 4.0 * N * (N + 1) * T_run * n_om
-    flops_screen = 0.5 * N ** 3 * 8.0 * n_om
-    per_step = {f"project_{pre}_kernel": flops_proj, f"herk_{pre}_kernel": flops_acc, "update_kernel": flops_screen,
+    sample_rows = shp.n_k * n_sample_occ if learned_path else 0
+    T_main, T_sample, fl = _pairs_and_flops(shp, cutoff, n_om, sample_rows, fallback)
+    per_step = {f"project_{pre}_kernel": fl["proj"], f"herk_{pre}_kernel": fl["acc"], "update_kernel": fl["screen"],
+                "project_rows_bf16_kernel": fl["sample"] if a.precision == "split_bf16" else 0.0,
                 "pair_product_kernel": 0.0, "scale_split_kernel": 0.0, "apply_kernel": 0.0}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dk = kernels[dom]
@@ -689,8 +748,9 @@ def main() -> int:
     achieved = alg_per_launch / (avg_ms * 1e-3) / 1e12
     peak_dtype = "fp64" if dom == "update_kernel" else ("bf16" if pre == "bf16" else ("fp16" if pre == "f16" else "fp32"))
     traffic = None
+    traffic_file = a.traffic or os.path.join(ROOT, "profiles", f"traffic_{a.workload}.json")
     try:
-        with open(a.traffic) as fh:
+        with open(traffic_file) as fh:
             tr = json.load(fh)
         if tr.get("kernel") == dom and tr.get("source_hash") == kernel_source_hash() and tr.get("workload") == a.workload:
             traffic = tr["bytes_per_launch"]
@@ -700,6 +760,9 @@ def main() -> int:
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[peak_dtype], 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4), "alg_flops_per_launch": alg_per_launch,
                 "launches": dk["launches"]}
+    if traffic is not None:
+        roofline["hbm_gbs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+        roofline["hbm_frac"] = round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_GBS, 4)
     if pre in ("bf16", "f16") and dom != "update_kernel":
         # a split product executes three 16-bit MFMA products per algorithmic one
         roofline["executed_tflops"] = round(3.0 * achieved, 2)
@@ -707,62 +770,149 @@ def main() -> int:
     breakdown = {k: round(v["total_ms"] / a.steps / 1e3, 4) for k, v in kernels.items()}
     log(f"kernels (s/step): {breakdown}; dominant {dom} at {achieved:.1f} TFLOP/s")
 
+    # ----------------------------------------------------------- W check (a7)
+    S = np.array(sorted(set([0, 1, 2, 17, N // 3, N // 2, N - 2, N - 1] + list(range(100, 108)))))
+    S = S[S < N]
+    Sg = torch.from_numpy(S).to(dev)
+    w_res = _w_residual(P, W, v_dev, Sg)
+    log(f"W residual of (1 - vP) W = v on {S.size} sampled rows: max {max(w_res):.2e}")
+    P_step_blk = _block(P, Sg)
+
+    # --------------------------------------------- learned path: model error (A19 ii)
+    model = None
+    P_ret_blk = None
+    y_gpu_free = None
+    if learned_path and not a.no_model_error:
+        tm = time.time()
+        pret = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision=a.precision, eps_dev=eps_dev,
+                                   kq=inp.kq, unocc_range=(0, cutoff))
+        wsr = torch.empty(pret.workspace_size(), dtype=torch.uint8, device=dev)
+        C = pret.run(wsr)
+        rest = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision=a.precision, eps_dev=eps_dev,
+                                   kq=inp.kq, unocc_range=(cutoff, shp.n_unocc))
+        del wsr
+        wsr = torch.empty(rest.workspace_size(), dtype=torch.uint8, device=dev)
+        B = rest.run(wsr)
+        torch.cuda.synchronize()
+        del wsr
+        t_all = time.time() - tm
+        P_ret_blk = _block(C, Sg)
+        p_ret_diag = torch.diagonal(C, dim1=1, dim2=2).real.cpu().numpy()
+        B.add_(C)                                    # the all-band sum, same path
+        trunc = _rel_per_omega(C, B)
+        corr = _rel_per_omega(P, B) if not fallback else np.zeros(n_om)
+        del C
+        P_all_blk = _block(B, Sg)
+        del B
+        torch.cuda.empty_cache()
+        model = {"corrected_vs_all_bands_per_omega": [float(x) for x in corr],
+                 "corrected_vs_all_bands_max": float(corr.max()), "corrected_vs_all_bands_mean": float(corr.mean()),
+                 "truncation_per_omega": [float(x) for x in trunc], "truncation_max": float(trunc.max()),
+                 "truncation_mean": float(trunc.mean()),
+                 "reference": f"explicit sum over all {shp.n_unocc} unoccupied bands on the same {a.precision} "
+                              f"path, outside the timed region ({t_all:.0f} s)",
+                 "meets_1e-4": bool(corr.max() <= 1e-4)}
+        log(f"model error vs all bands: max {corr.max():.4f} mean {corr.mean():.4f} (truncation alone: max "
+            f"{trunc.max():.4f} mean {trunc.mean():.4f}); all-band pass {t_all:.0f} s")
+
     # ------------------------------------------------- FP32 plain path, all bands
     compare = None
     if not a.no_compare:
-        occ_s = 4 if a.workload == "c5" else 8
-        cmp_call = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision="fp32", eps_dev=eps_dev,
-                                       kq=inp.kq, k_list=[0], occ_range=(0, occ_s))
+        if a.fp32_full:
+            cmp_call = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision="fp32", eps_dev=eps_dev,
+                                           kq=inp.kq)
+            occ_s, ks, scale = shp.n_occ, None, 1.0
+            sample_txt = "all k-points, all occupied x all unoccupied bands (not extrapolated)"
+        else:
+            occ_s = 4 if a.workload == "c5" else 8
+            cmp_call = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision="fp32", eps_dev=eps_dev,
+                                           kq=inp.kq, k_list=[0], occ_range=(0, occ_s))
+            scale = shp.n_k * shp.n_occ / occ_s
+            sample_txt = f"k=0, occupied 0..{occ_s - 1}, all {shp.n_unocc} unoccupied, scaled x{scale:g}"
         cws = torch.empty(cmp_call.workspace_size(), dtype=torch.uint8, device=dev)
-        cmp_call.run(cws)
-        torch.cuda.synchronize()
+        if not a.fp32_full:
+            cmp_call.run(cws)
+            torch.cuda.synchronize()
         c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         c0.record()
         cmp_call.run(cws)
         c1.record()
         torch.cuda.synchronize()
         cms = c0.elapsed_time(c1)
-        scale = shp.n_k * shp.n_occ / occ_s
-        pairs = occ_s * shp.n_unocc
-        fl = 8.0 * N * shp.R * pairs + 4.0 * N * (N + 1) * pairs * n_om
+        pairs = (shp.n_k if a.fp32_full else 1) * occ_s * shp.n_unocc
+        fl32 = 8.0 * N * shp.R * pairs + 4.0 * N * (N + 1) * pairs * n_om
         fp32_s = cms / 1e3 * scale
-        compare = {"fp32_plain_all_bands_s_per_qpoint": round(fp32_s, 2), "sample": f"k=0, occupied 0..{occ_s - 1}, "
-                   f"all {shp.n_unocc} unoccupied, scaled x{scale:g}", "fp32_tflops": round(fl / cms / 1e9, 1),
-                   "fp32_frac_of_fp32_mfma_peak": round(fl / cms / 1e9 / PEAK_TFLOPS["fp32"], 4),
+        compare = {"fp32_plain_all_bands_s_per_qpoint": round(fp32_s, 2), "sample": sample_txt,
+                   "fp32_tflops": round(fl32 / cms / 1e9, 1),
+                   "fp32_frac_of_fp32_mfma_peak": round(fl32 / cms / 1e9 / PEAK_TFLOPS["fp32"], 4),
                    "speedup_vs_fp32_plain": round(fp32_s / (ms / 1e3), 2)}
-        log(f"fp32 plain path: {fp32_s:.1f} s/q-point (extrapolated), {fl / cms / 1e9:.1f} TFLOP/s")
+        log(f"fp32 plain path: {fp32_s:.1f} s/q-point ({'measured in full' if a.fp32_full else 'extrapolated'}), "
+            f"{fl32 / cms / 1e9:.1f} TFLOP/s")
         del cws, cmp_call
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ oracle legs
-    parity = None
+    parity = {"w_residual_per_omega": w_res, "w_residual_max": max(w_res),
+              "w_check": f"rows S of (1 - vP) W = v, |S|={S.size}, relative to ||v_S||"}
     cpu = None
     if not a.no_cpu:
         from oracle import polarization as orc
-        # sampled parity: the I,J in S block of P for a sample of pairs, GPU vs oracle
+        kk = int(inp.kq[0])
         occ_p = 2
-        S = np.array(sorted(set([0, 1, 2, 17, N // 3, N // 2, N - 2, N - 1] + list(range(100, 108)))))
+        U_S = U[Sg].cpu().numpy().astype(np.complex128)
+        # explicit bands, 2 occupied bands of k = 0: GPU pass vs oracle on the sampled block
         par = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision=a.precision, eps_dev=eps_dev,
                                   kq=inp.kq, k_list=[0], occ_range=(0, occ_p), unocc_range=(0, cutoff))
         pws = torch.empty(par.workspace_size(), dtype=torch.uint8, device=dev)
-        Ps = par.run(pws)
-        torch.cuda.synchronize()
-        Sg = torch.from_numpy(S).to(dev)
-        Pblk = Ps[:, Sg][:, :, Sg].cpu().numpy()
-        kk = int(inp.kq[0])
-        U_S = U[Sg].cpu().numpy().astype(np.complex128)
+        Pblk = _block(par.run(pws), Sg)
+        del pws, par
         psi_h = np.zeros((shp.n_k, shp.n_bands, shp.R), dtype=np.complex64)  # only the needed rows are filled
         psi_h[0, :occ_p] = psi[0, :occ_p].cpu().numpy()
-        psi_h[kk, shp.n_occ:shp.n_occ + cutoff] = psi[kk, shp.n_occ:shp.n_occ + cutoff].cpu().numpy()
+        psi_h[kk, shp.n_occ:] = psi[kk, shp.n_occ:].cpu().numpy()
         tp = time.time()
         Pref = orc.polarization(U_S, psi_h, inp.eps, inp.omega, shp.n_occ, kq=inp.kq, k_list=[0],
                                 occ_range=(0, occ_p), unocc_range=(0, cutoff))
         err = orc.rel_fro(Pblk, Pref)
-        parity = {"max_rel_fro_err": float(err.max()), "sample": f"P[I,J] for |S|={S.size} sampled I,J, k=0, "
-                  f"occupied 0..{occ_p - 1}, unoccupied 0..{cutoff - 1}, all {n_om} frequencies",
-                  "oracle_s": round(time.time() - tp, 1)}
-        log(f"sampled parity vs oracle: max rel err {err.max():.2e}")
-        del pws, par, Ps
+        parity["explicit_bands"] = {"max_rel_fro_err": float(err.max()), "per_omega": [float(x) for x in err],
+                                    "sample": f"P[I,J] for |S|={S.size} sampled I,J, k=0, occupied 0..{occ_p - 1}, "
+                                              f"unoccupied 0..{cutoff - 1}, all {n_om} frequencies",
+                                    "oracle_s": round(time.time() - tp, 1)}
+        parity["max_rel_fro_err"] = float(err.max())
+        log(f"sampled parity vs oracle (explicit bands): max rel err {err.max():.2e}")
+        if learned_path:
+            # the left-out bands on the same block (the all-band reference's other part)
+            par = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision=a.precision,
+                                      eps_dev=eps_dev, kq=inp.kq, k_list=[0], occ_range=(0, occ_p),
+                                      unocc_range=(cutoff, shp.n_unocc))
+            pws = torch.empty(par.workspace_size(), dtype=torch.uint8, device=dev)
+            Pblk = _block(par.run(pws), Sg)
+            del pws, par
+            Pref = orc.polarization(U_S, psi_h, inp.eps, inp.omega, shp.n_occ, kq=inp.kq, k_list=[0],
+                                    occ_range=(0, occ_p), unocc_range=(cutoff, shp.n_unocc))
+            err = orc.rel_fro(Pblk, Pref)
+            parity["left_out_bands"] = {"max_rel_fro_err": float(err.max()), "per_omega": [float(x) for x in err],
+                                        "sample": f"as above, unoccupied {cutoff}..{shp.n_unocc - 1}"}
+            log(f"sampled parity vs oracle (left-out bands): max rel err {err.max():.2e}")
+            if not fallback and P_ret_blk is not None:
+                # the correction step on the GPU's own P_ret (A19 (i)): oracle features from its
+                # diagonal, FP64 perceptron with the same BF16-valued weights, congruence on the block
+                from oracle import mlp as omlp
+                from oracle import surrogate as osg
+                from oracle.precision import round_bf16
+                prm = surrogate.mlp.to_dict()
+                for k in ("W1", "W2", "W3"):
+                    prm[k] = round_bf16(prm[k]).astype(np.float64)
+                X = osg.features(_diag_view(p_ret_diag.astype(np.complex128)), inp.eps, inp.omega, shp.n_occ,
+                                 cutoff, inp.kq, n_in=surrogate.mlp.n_in)
+                y = omlp.forward(prm, X)[:, 0].reshape(n_om, N)
+                ref = osg.apply(P_ret_blk, y[:, S].reshape(-1))
+                err = orc.rel_fro(P_step_blk, ref)
+                parity["correction_step"] = {"max_rel_fro_err": float(err.max()), "per_omega": [float(x) for x in err],
+                                             "sample": "the step's corrected P on the block against the oracle's "
+                                                       "features, FP64 perceptron and congruence applied to the "
+                                                       "GPU's explicit-band P"}
+                parity["max_rel_fro_err"] = max(parity["max_rel_fro_err"], float(err.max()))
+                log(f"correction step vs oracle: max rel err {err.max():.2e}")
         # cpu baseline: the oracle on one occupied band x m unoccupied bands (full basis)
         U_h = U.cpu().numpy().astype(np.complex128)
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -775,6 +925,7 @@ def main() -> int:
                 blas = f"{pools[0].get('internal_api')} BLAS, {cores} threads"
         except ImportError:
             pass
+
         def oracle_time(m):
             tc = time.time()
             orc.polarization(U_h, psi_h, inp.eps, inp.omega, shp.n_occ, kq=inp.kq, k_list=[0], occ_range=(0, 1),
@@ -789,37 +940,46 @@ def main() -> int:
         orc.polarization(U_h, psi_h, inp.eps, inp.omega, shp.n_occ, kq=inp.kq, k_list=[0], occ_range=(0, o2),
                          unocc_range=(0, m2))
         dt2 = time.time() - tc
+        T_pairs = shp.n_k * shp.n_occ * cutoff
         scale = T_pairs / (o2 * m2)
         cpu = {"value": round(dt2 * scale, 1), "unit": "s/q-point", "cores": cores, "kind": "oracle",
                "sample": f"k=0, occupied 0..{o2 - 1} x unoccupied 0..{m2 - 1} ({o2 * m2} pairs, full basis, all "
-                         f"{n_om} frequencies) in {dt2:.1f} s ({blas}), scaled x{scale:.0f} to the {T_pairs} pairs "
-                         f"of a q-point"}
+                         f"{n_om} frequencies) in {dt2:.1f} s ({blas}), scaled x{scale:.0f} to the {T_pairs} "
+                         f"explicit pairs of a q-point"}
         log(f"cpu oracle: {dt2:.1f} s for {o2 * m2} pairs -> {dt2 * scale:.0f} s/q-point extrapolated")
         del U_h
 
+    numeric_ok = parity.get("max_rel_fro_err", 1.0) <= 1e-4 and max(w_res) <= 1e-8 and screening_ok
     out = {
         "metric": "P(q,iw) s/q-point: split-BF16+surrogate vs FP32 plain @ rel err<=1e-4",
         "value": round(ms / 1e3, 4),
         "unit": "s/q-point",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 2),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
         "dtype": {"split_bf16": "bf16x3 (split hi/lo), fp32 acc, fp64 P/W", "split_fp16": "fp16x3 (split), fp32 acc",
                   "fp32": "fp32"}[a.precision],
         "data": "synthetic (seeded; paper-shaped)",
         "config": {"workload": f"{a.workload}: N_k={shp.n_k}, N={N}, R={shp.R}, {shp.n_occ} occ + {shp.n_unocc} "
                                f"unocc bands, {n_om} imaginary frequencies, explicit bands to {cutoff}",
-                   "precision": a.precision, "surrogate": surrogate is not None,
-                   "surrogate_judge": sur_report or None,
-                   "step": "P (projection + accumulation) + surrogate + W (FP64 screening)",
+                   "precision": a.precision, "surrogate": learned_path,
+                   "surrogate_judge": ({**sur_report, "n_sample_occ": n_sample_occ, "judge_tol": a.judge_tol}
+                                       if learned_path else None),
+                   "step": ("P (explicit bands, learned correction, judge sample) + W (FP64 screening)"
+                            if learned_path else "P (all bands) + W (FP64 screening)"),
                    **({"tuning": a.tuning} if a.tuning else {})},
+        "pairs_per_step": {"explicit": T_main, "judge_sample_projected": T_sample},
         "kernels_s_per_step": breakdown,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp32_compare": compare,
         "parity": parity,
+        "model_error": model,
+        "rel_err_bar_met": {"numeric_parity_vs_oracle": bool(numeric_ok),
+                            "model_vs_all_bands": (model["meets_1e-4"] if model else None)},
+        "screening_ok": screening_ok,
     }
     print(json.dumps(out))
-    return 0
+    return 0 if screening_ok else 3
 
 
 if __name__ == "__main__":

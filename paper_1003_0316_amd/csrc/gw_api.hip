@@ -297,7 +297,7 @@ int validate_learned(const gw_pol_desc* dp, const gw_learned_desc* l) {
 // kernels' scratch, the judge's projections and partial traces, the errors and
 // the finite-check flag.
 struct LearnedLayout {
-  size_t pol, x, y, act, sws, mproj, pws, part, err, total;
+  size_t pol, x, y, act, sws, mproj, pws, pws_bytes, part, err, total;
   int nu, parts_row;
 };
 
@@ -336,6 +336,7 @@ LearnedLayout learned_layout(const gw_pol_desc& d, const gw_learned_desc& l) {
   L.sws = cv.off; cv.take<char>(sws);
   L.mproj = cv.off; cv.take<char>(mproj);
   L.pws = cv.off; cv.take<char>(pws);
+  L.pws_bytes = pws;
   L.part = cv.off; cv.take<double>((size_t)std::max(1, n_rows) * L.parts_row * d.n_omega);
   L.err = cv.off; cv.take<double>(kMaxOmega);
   cv.take<char>(kFlagBytes);
@@ -405,7 +406,7 @@ int polarization_learned(hipStream_t s, const gw_pol_desc& d, const gw_learned_d
           st = launch_project_f64(s, d.N, d.R, static_cast<const double2*>(d.U), static_cast<const double2*>(po),
                                   static_cast<const double2*>(pu), L.nu, 0, L.nu, static_cast<double2*>(M), L.nu);
         } else {
-          st = mfma_project(s, d.precision, d.N, d.R, 1, L.nu, d.U, po, pu, M, ws + L.pws, L.err - L.pws);
+          st = mfma_project(s, d.precision, d.N, d.R, 1, L.nu, d.U, po, pu, M, ws + L.pws, L.pws_bytes);
         }
         if (st != GW_OK) return st;
         if ((st = launch_sample_trace(s, d.precision == GW_FP64, M, d.N, L.nu, L.nu, d.eps + (size_t)k * nb + n,

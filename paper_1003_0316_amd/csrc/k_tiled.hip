@@ -1319,7 +1319,7 @@ int tiled_project(hipStream_t s, int N, int R, int n_occ, int n_unocc, const flo
   a.T = T;
   a.M = M;
   a.ldm = T;
-  return launch_gemm<OUT_ROWS>(s, a, d.nI * a.nTj, "project_bf16_kernel");
+  return launch_gemm<OUT_ROWS>(s, a, d.nI * a.nTj, "project_rows_bf16_kernel");
 }
 
 int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
