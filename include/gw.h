@@ -53,12 +53,17 @@ extern "C" {
  *                  lo = bf16(x - hi) (round to nearest even) and a product is
  *                  hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation.
  *   GW_SPLIT_FP16  as SPLIT_BF16 with FP16 words; lo is pre-scaled by 2^11 and
- *                  accumulated separately so it stays in FP16's normal range. */
+ *                  accumulated separately so it stays in FP16's normal range.
+ *   GW_FP16        ablation: single FP16 products (the hi words of
+ *                  GW_SPLIT_FP16, same power-of-two scaling, no lo words);
+ *                  about 3e-4 relative error, above the 1e-4 bar of the
+ *                  reduced-precision paths. */
 typedef enum gw_precision {
   GW_FP64 = 0,
   GW_FP32 = 1,
   GW_SPLIT_BF16 = 2,
-  GW_SPLIT_FP16 = 3
+  GW_SPLIT_FP16 = 3,
+  GW_FP16 = 4
 } gw_precision;
 
 typedef enum gw_status {
@@ -94,7 +99,7 @@ int gw_version(void);
  * gw_project: M[I][n*n_unocc + n'] = sum_r U[I][r] conj(psi_occ[n][r]) psi_unocc[n'][r]
  * (Eq. proj_MB).
  *   precision  GW_FP64: U, psi_occ, psi_unocc, M are c128.
- *              GW_FP32 / GW_SPLIT_BF16 / GW_SPLIT_FP16: inputs c64, M c64.
+ *              GW_FP32 / GW_SPLIT_BF16 / GW_SPLIT_FP16 / GW_FP16: inputs c64, M c64.
  *   U          [N][R];  psi_occ [n_occ][R];  psi_unocc [n_unocc][R]
  *   M          [N][n_occ*n_unocc] (output, overwritten)
  *   N, R, n_occ, n_unocc >= 1.  ws/ws_bytes: workspace from

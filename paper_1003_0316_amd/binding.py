@@ -23,8 +23,9 @@ if not os.path.exists(LIB_PATH):
                       f"`python -m paper_1003_0316_amd.build` (no CPU fallback exists)")
 _lib = ctypes.CDLL(LIB_PATH)
 
-GW_FP64, GW_FP32, GW_SPLIT_BF16, GW_SPLIT_FP16 = 0, 1, 2, 3
-PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "split_bf16": GW_SPLIT_BF16, "split_fp16": GW_SPLIT_FP16}
+GW_FP64, GW_FP32, GW_SPLIT_BF16, GW_SPLIT_FP16, GW_FP16 = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "split_bf16": GW_SPLIT_BF16, "split_fp16": GW_SPLIT_FP16,
+              "fp16": GW_FP16}
 STATUS = {0: "GW_OK", -1: "GW_ERR_INVALID_ARG", -2: "GW_ERR_UNSUPPORTED", -3: "GW_ERR_WORKSPACE",
           -4: "GW_ERR_HIP", -5: "GW_ERR_NONFINITE", -6: "GW_ERR_NOT_HPD"}
 GW_CHECK_FINITE, GW_CHECK_HPD = 1, 2

@@ -24,7 +24,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 namespace {
 
-bool valid_precision(int p) { return p >= GW_FP64 && p <= GW_SPLIT_FP16; }
+bool valid_precision(int p) { return p >= GW_FP64 && p <= GW_FP16; }
 size_t cplx_bytes(int p) { return p == GW_FP64 ? 16 : 8; }
 
 // Chunk size for one polarization call.
@@ -157,8 +157,8 @@ int validate_desc(const gw_pol_desc* dp) {
   if (d.n_nodes > 0) {
     if (d.n_nodes < 2 || d.n_nodes > kMaxSlots)
       return fail(GW_ERR_INVALID_ARG, "gw_polarization: the spectral route needs 2..256 nodes");
-    if (d.precision == GW_SPLIT_FP16 && d.n_nodes > kMaxOmega)
-      return fail(GW_ERR_UNSUPPORTED, "gw_polarization: at most 64 nodes with GW_SPLIT_FP16");
+    if ((d.precision == GW_SPLIT_FP16 || d.precision == GW_FP16) && d.n_nodes > kMaxOmega)
+      return fail(GW_ERR_UNSUPPORTED, "gw_polarization: at most 64 nodes with the FP16 precisions");
     if (!d.nodes_host) return fail(GW_ERR_INVALID_ARG, "gw_polarization: nodes_host is NULL");
     for (int b = 0; b < d.n_nodes; ++b)
       if (!std::isfinite(d.nodes_host[b]) || d.nodes_host[b] <= 0.0 || (b > 0 && d.nodes_host[b] <= d.nodes_host[b - 1]))
@@ -496,8 +496,8 @@ int gw_polarization_workspace_size(const gw_pol_desc* d, size_t* bytes) {
     return fail(GW_ERR_UNSUPPORTED, "gw_polarization: real inputs are supported with GW_SPLIT_BF16 only");
   if (d->n_nodes < 0 || d->n_nodes == 1 || d->n_nodes > kMaxSlots)
     return fail(GW_ERR_INVALID_ARG, "gw_polarization: the spectral route needs 2..256 nodes");
-  if (d->n_nodes > kMaxOmega && d->precision == GW_SPLIT_FP16)
-    return fail(GW_ERR_UNSUPPORTED, "gw_polarization: at most 64 nodes with GW_SPLIT_FP16");
+  if (d->n_nodes > kMaxOmega && (d->precision == GW_SPLIT_FP16 || d->precision == GW_FP16))
+    return fail(GW_ERR_UNSUPPORTED, "gw_polarization: at most 64 nodes with the FP16 precisions");
   *bytes = make_plan(*d).ws;
   return GW_OK;
 }

@@ -272,7 +272,11 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
-enum Word { W_BF16 = 0, W_F16 = 1 };
+// Operand words: BF16 hi + lo; FP16 hi + lo (power-of-two scaled, lo kept in
+// range by 2^11 and accumulated apart); FP16 hi alone (the single-precision
+// ablation: same scaling, no lo words and no correction products).
+enum Word { W_BF16 = 0, W_F16 = 1, W_F16S = 2 };
+constexpr bool is_f16(int w) { return w != W_BF16; }
 
 template <int WORD>
 __device__ inline void split_word(float re, float im, float s, uint32_t& hi, uint32_t& lo) {
@@ -284,15 +288,19 @@ __device__ inline void split_word(float re, float im, float s, uint32_t& hi, uin
   } else {
     float a = re * s, b = im * s;
     halfx2 h = {(_Float16)a, (_Float16)b};
-    halfx2 l = {(_Float16)((a - (float)h[0]) * 2048.f), (_Float16)((b - (float)h[1]) * 2048.f)};
     hi = __builtin_bit_cast(uint32_t, h);
-    lo = __builtin_bit_cast(uint32_t, l);
+    if constexpr (WORD == W_F16) {
+      halfx2 l = {(_Float16)((a - (float)h[0]) * 2048.f), (_Float16)((b - (float)h[1]) * 2048.f)};
+      lo = __builtin_bit_cast(uint32_t, l);
+    } else {
+      lo = 0u;
+    }
   }
 }
 
 template <int WORD>
 __device__ inline floatx16 mma16(uint4 a, uint4 b, floatx16 c) {
-  if constexpr (WORD == W_BF16)
+  if constexpr (!is_f16(WORD))
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
                                                    0, 0, 0);
   else
@@ -365,6 +373,7 @@ __device__ inline void mma_stage16(const Lds16& L, AccF32& acc, AccF32& acc2, in
         acc.r[rb][cb] = mma16<WORD>(ah[rb], brh[cb], acc.r[rb][cb]);
         acc.i[rb][cb] = mma16<WORD>(ah[rb], bih[cb], acc.i[rb][cb]);
       }
+    if constexpr (WORD == W_F16S) continue;
     AccF32& c2 = (WORD == W_BF16) ? acc : acc2;
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
@@ -409,7 +418,7 @@ __global__ void zero_u32_kernel(unsigned* __restrict__ p, int n) {
 template <int WORD>
 __global__ void split_u_kernel(int N, int R, int Rp, const float2* __restrict__ U, const Scales* __restrict__ sc,
                                uint32_t* __restrict__ hi, uint32_t* __restrict__ lo) {
-  const float s = WORD == W_F16 ? pow2_scale(__uint_as_float(sc->u)) : 1.f;
+  const float s = is_f16(WORD) ? pow2_scale(__uint_as_float(sc->u)) : 1.f;
   size_t n = (size_t)N * Rp;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     int i = (int)(e / Rp), r = (int)(e % Rp);
@@ -423,7 +432,7 @@ __global__ void split_u_kernel(int N, int R, int Rp, const float2* __restrict__ 
 
 // Projection with pre-split U and products split while staging.
 template <int WORD>
-__global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void project16_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
+__global__ __launch_bounds__(NT, WORD == W_F16 ? 1 : 2) void project16_kernel(int N, int R, int Rp, const uint32_t* __restrict__ Uh,
                                                           const uint32_t* __restrict__ Ul,
                                                           const float2* __restrict__ po,
                                                           const float2* __restrict__ pu, int nu, long tb, int T,
@@ -434,7 +443,7 @@ __global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void project16_kernel(i
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   float sF = 1.f, unscale = 1.f;
-  if constexpr (WORD == W_F16) {
+  if constexpr (is_f16(WORD)) {
     const float mp = __uint_as_float(sc->psi);
     sF = pow2_scale(2.f * mp * mp);
     unscale = 1.f / (pow2_scale(__uint_as_float(sc->u)) * sF);
@@ -531,15 +540,19 @@ __global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void project16_kernel(i
         if (gi < N) {
           float re = acc.r[rb][cb][v], im = acc.i[rb][cb][v];
           if constexpr (WORD == W_F16) {
-            re = (re + acc2.r[rb][cb][v] * (1.f / 2048.f)) * unscale;
-            im = (im + acc2.i[rb][cb][v] * (1.f / 2048.f)) * unscale;
+            re += acc2.r[rb][cb][v] * (1.f / 2048.f);
+            im += acc2.i[rb][cb][v] * (1.f / 2048.f);
+          }
+          if constexpr (is_f16(WORD)) {
+            re *= unscale;
+            im *= unscale;
             mloc = fmaxf(mloc, fmaxf(fabsf(re), fabsf(im)));
           }
           M[(size_t)gi * ldm + gt] = make_float2(re, im);
         }
       }
     }
-  if constexpr (WORD == W_F16) {
+  if constexpr (is_f16(WORD)) {
     // block maximum of |M| for the accumulation's scale
     __shared__ float red[NT];
     red[tid] = mloc;
@@ -554,7 +567,7 @@ __global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void project16_kernel(i
 
 // Accumulation with both operands split while staging.
 template <int WORD>
-__global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void herk16_kernel(int N, int T, const float2* __restrict__ M,
+__global__ __launch_bounds__(NT, WORD == W_F16 ? 1 : 2) void herk16_kernel(int N, int T, const float2* __restrict__ M,
                                                                             long ldm, const float* __restrict__ w,
                                                                             double2* __restrict__ P,
                                                                             const Scales* __restrict__ sc) {
@@ -567,7 +580,7 @@ __global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void herk16_kernel(int 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
   float sA = 1.f, sB = 1.f, unscale = 1.f;
-  if constexpr (WORD == W_F16) {
+  if constexpr (is_f16(WORD)) {
     const float mm = __uint_as_float(sc->m);
     sA = pow2_scale(mm * __uint_as_float(sc->w[om]));
     sB = pow2_scale(mm);
@@ -631,8 +644,12 @@ __global__ __launch_bounds__(NT, WORD == W_BF16 ? 2 : 1) void herk16_kernel(int 
         if (gi < N) {
           double re = acc.r[rb][cb][v], im = acc.i[rb][cb][v];
           if constexpr (WORD == W_F16) {
-            re = (re + (double)acc2.r[rb][cb][v] * (1.0 / 2048.0)) * unscale;
-            im = (im + (double)acc2.i[rb][cb][v] * (1.0 / 2048.0)) * unscale;
+            re += (double)acc2.r[rb][cb][v] * (1.0 / 2048.0);
+            im += (double)acc2.i[rb][cb][v] * (1.0 / 2048.0);
+          }
+          if constexpr (is_f16(WORD)) {
+            re *= unscale;
+            im *= unscale;
           }
           double2 p = Pj[(size_t)gi * N + gj];
           p.x += re;
@@ -914,7 +931,7 @@ int launch_maxabs(hipStream_t s, const float2* x, size_t n, unsigned* out) {
 int prepare_split(hipStream_t s, int word, int N, int R, int Rp, const float2* U, const float2* psi, size_t n_psi,
                   uint32_t* hi, uint32_t* lo, Scales* sc) {
   int st;
-  if (word == W_F16) {
+  if (word != W_BF16) {
     if ((st = launch_zero_u32(s, reinterpret_cast<unsigned*>(sc), (int)(sizeof(Scales) / 4))) != GW_OK) return st;
     if ((st = launch_maxabs(s, U, (size_t)N * R, &sc->u)) != GW_OK) return st;
     if ((st = launch_maxabs(s, psi, n_psi, &sc->psi)) != GW_OK) return st;
@@ -923,8 +940,10 @@ int prepare_split(hipStream_t s, int word, int N, int R, int Rp, const float2* U
   unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
   if (word == W_BF16)
     hipLaunchKernelGGL(split_u_kernel<W_BF16>, dim3(blocks), dim3(256), 0, s, N, R, Rp, U, sc, hi, lo);
-  else
+  else if (word == W_F16)
     hipLaunchKernelGGL(split_u_kernel<W_F16>, dim3(blocks), dim3(256), 0, s, N, R, Rp, U, sc, hi, lo);
+  else
+    hipLaunchKernelGGL(split_u_kernel<W_F16S>, dim3(blocks), dim3(256), 0, s, N, R, Rp, U, sc, hi, lo);
   GW_LAUNCHED("split_u_kernel");
   return GW_OK;
 }
@@ -950,9 +969,12 @@ int launch_herk16(hipStream_t s, int word, int N, int T, const float2* M, long l
   if (word == W_BF16) {
     ProfScope prof(s, "herk_bf16_kernel");
     hipLaunchKernelGGL(herk16_kernel<W_BF16>, hgrid, dim3(NT), 0, s, N, T, M, ldm, w, P, sc);
-  } else {
+  } else if (word == W_F16) {
     ProfScope prof(s, "herk_f16_kernel");
     hipLaunchKernelGGL(herk16_kernel<W_F16>, hgrid, dim3(NT), 0, s, N, T, M, ldm, w, P, sc);
+  } else {
+    ProfScope prof(s, "herk_f16s_kernel");
+    hipLaunchKernelGGL(herk16_kernel<W_F16S>, hgrid, dim3(NT), 0, s, N, T, M, ldm, w, P, sc);
   }
   GW_LAUNCHED("herk16_kernel");
   return GW_OK;
@@ -974,9 +996,13 @@ int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32
   if (word == W_BF16) {
     ProfScope prof(s, "project_bf16_kernel");
     hipLaunchKernelGGL(project16_kernel<W_BF16>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, nu, tb, T, M, ldm, sc);
-  } else {
+  } else if (word == W_F16) {
     ProfScope prof(s, "project_f16_kernel");
     hipLaunchKernelGGL(project16_kernel<W_F16>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, nu, tb, T, M, ldm, sc);
+  } else {
+    ProfScope prof(s, "project_f16s_kernel");
+    hipLaunchKernelGGL(project16_kernel<W_F16S>, grid, dim3(NT), 0, s, N, R, Rp, Uh, Ul, po, pu, nu, tb, T, M, ldm,
+                       sc);
   }
   GW_LAUNCHED("project16_kernel");
   return GW_OK;
@@ -1026,7 +1052,9 @@ size_t mfma_project_workspace(int precision, int N, int R, int n_occ, int n_unoc
   return split_u_bytes(precision, N, R);
 }
 
-static int word_of(int precision) { return precision == GW_SPLIT_FP16 ? W_F16 : W_BF16; }
+static int word_of(int precision) {
+  return precision == GW_SPLIT_FP16 ? W_F16 : (precision == GW_FP16 ? W_F16S : W_BF16);
+}
 
 int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_unocc, const void* U,
                  const void* psi_occ, const void* psi_unocc, void* M, void* ws, size_t ws_bytes) {
@@ -1045,7 +1073,7 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
   uint32_t* Ul = cv.take<uint32_t>((size_t)N * Rp);
   Scales* sc = cv.take<Scales>(1);
   int st;
-  if (word == W_F16) {
+  if (word != W_BF16) {
     // psi_occ and psi_unocc are separate arrays: take the larger of their maxima
     if ((st = launch_zero_u32(s, reinterpret_cast<unsigned*>(sc), (int)(sizeof(Scales) / 4))) != GW_OK) return st;
     if ((st = launch_maxabs(s, static_cast<const float2*>(psi_occ), (size_t)n_occ * R, &sc->psi)) != GW_OK) return st;
@@ -1054,8 +1082,12 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
     if ((st = launch_maxabs(s, static_cast<const float2*>(U), (size_t)N * R, &sc->u)) != GW_OK) return st;
     size_t n = (size_t)N * Rp;
     unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 16384);
-    hipLaunchKernelGGL(split_u_kernel<W_F16>, dim3(blocks), dim3(256), 0, s, N, R, Rp,
-                       static_cast<const float2*>(U), sc, Uh, Ul);
+    if (word == W_F16)
+      hipLaunchKernelGGL(split_u_kernel<W_F16>, dim3(blocks), dim3(256), 0, s, N, R, Rp,
+                         static_cast<const float2*>(U), sc, Uh, Ul);
+    else
+      hipLaunchKernelGGL(split_u_kernel<W_F16S>, dim3(blocks), dim3(256), 0, s, N, R, Rp,
+                         static_cast<const float2*>(U), sc, Uh, Ul);
     GW_LAUNCHED("split_u_kernel");
   } else if ((st = prepare_split(s, word, N, R, Rp, static_cast<const float2*>(U), nullptr, 0, Uh, Ul, sc)) != GW_OK) {
     return st;
@@ -1092,7 +1124,7 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
     return st;
   for (const Chunk& c : chunks) {
     const int T = c.pairs();
-    if (word == W_F16 && split) {
+    if (word != W_BF16 && split) {
       // per-chunk maxima of |M| and |w_j|
       if ((st = launch_zero_u32(s, &sc->m, 1 + kMaxOmega)) != GW_OK) return st;
       hipLaunchKernelGGL(weights_f32_max_kernel, dim3((T + 255) / 256), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om,

@@ -55,3 +55,27 @@ def test_pmc_summary_scales_by_the_copy_calibration(tmp_path):
     assert t["bytes_per_launch"] == 200.0 * 1024 * 2.0 + 10.0 * 1024
     assert t["kernels"]["gemm8_bf16x3_kernel<2, false>"]["fetch_bytes_per_launch"] == 50.0 * 1024 * 2.0
     assert len(t["source_hash"]) == 16
+
+
+def test_block_error_estimate_weights_diagonal_and_off_diagonal():
+    """A block of sampled rows and columns over-weights the diagonal; the
+    estimate rescales the block's diagonal and off-diagonal errors by the whole
+    matrix's norms and recovers the full-matrix error."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    rng = np.random.default_rng(0)
+    N, n_om = 400, 3
+    A = rng.normal(size=(n_om, N, N)) + 1j * rng.normal(size=(n_om, N, N))
+    P = 0.05 * (A + np.conj(np.transpose(A, (0, 2, 1)))) + np.eye(N)[None] * 30.0
+    noise = rng.normal(size=P.shape) + 1j * rng.normal(size=P.shape)
+    eye = np.eye(N, dtype=bool)
+    X = P + np.where(eye[None], 1e-6, 1e-3) * np.abs(P) * noise      # large off-diagonal errors
+    full = np.linalg.norm((X - P).reshape(n_om, -1), axis=1) / np.linalg.norm(P.reshape(n_om, -1), axis=1)
+    S = np.sort(rng.choice(N, 32, replace=False))
+    D = np.linalg.norm(np.diagonal(X, axis1=1, axis2=2), axis=1)
+    F = np.linalg.norm(X.reshape(n_om, -1), axis=1)
+    be = bench._block_errors(X[:, S][:, :, S], P[:, S][:, :, S], (D, F))
+    est = np.array(be["full_matrix_estimate_per_omega"])
+    assert np.all(np.abs(est / full - 1) < 0.15), (est, full)
+    assert be["max_rel_fro_err"] < 0.5 * full.min()                    # the plain block error is biased low

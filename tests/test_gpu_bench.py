@@ -42,6 +42,8 @@ def test_bench_json_contract_small_workload():
     par = d["parity"]
     assert par["max_rel_fro_err"] < 1e-4
     assert len(par["explicit_bands"]["per_omega"]) == 13 and max(par["explicit_bands"]["per_omega"]) < 1e-4
+    assert par["explicit_bands"]["full_matrix_estimate_max"] < 1e-4
+    assert len(par["explicit_bands"]["offdiag_per_omega"]) == 13
     assert len(par["w_residual_per_omega"]) == 13 and par["w_residual_max"] < 1e-8
     assert d["screening_ok"] is True and d["rel_err_bar_met"]["numeric_parity_vs_oracle"] is True
     assert d["model_error"] is None

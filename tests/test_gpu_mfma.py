@@ -187,3 +187,27 @@ def test_extreme_shapes_max_frequencies(lib, real, N, R):
     ref = orc.polarization(U64, p64, inp.eps, om, 2, kq=inp.kq)
     err = orc.rel_fro(P.cpu().numpy(), ref)
     assert err.max() < TOL, err.max()
+
+
+def test_single_fp16_ablation_misses_the_bar(lib):
+    """GW_FP16 (hi words only, the split path's scaling): the ablation that
+    motivates the split.  Its error sits well above the split FP16 error and
+    around the 1e-4 bar; P stays Hermitian."""
+    import torch
+    shape = dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150)
+    inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=9, omega=gwsynth.omega_mesh("m16"))
+    U, psi = _dev(inp)
+    Ur, pr = _rounded(inp)
+    ref = orc.polarization(Ur, pr, inp.eps, inp.omega, 3, kq=inp.kq)
+    P1 = lib.gw_polarization(U, psi, inp.eps, inp.omega, 3, precision="fp16", kq=inp.kq).cpu().numpy()
+    P2 = lib.gw_polarization(U, psi, inp.eps, inp.omega, 3, precision="split_fp16", kq=inp.kq).cpu().numpy()
+    M1 = lib.gw_project(U, psi[0, :3].contiguous(), psi[0, 3:].contiguous(), "fp16").cpu().numpy()
+    torch.cuda.synchronize()
+    e1, e2 = orc.rel_fro(P1, ref), orc.rel_fro(P2, ref)
+    mref = orc.projections(Ur, pr[0, :3], pr[0, 3:])
+    em = np.linalg.norm(M1 - mref) / np.linalg.norm(mref)
+    print(f"single FP16: P max rel err {e1.max():.2e} (split FP16 {e2.max():.2e}), projection {em:.2e}")
+    assert 2e-5 < e1.max() < 5e-3 and e2.max() < 0.1 * e1.max()
+    assert 5e-5 < em < 2e-3
+    for j in range(P1.shape[0]):
+        assert np.array_equal(P1[j], P1[j].conj().T)
