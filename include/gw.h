@@ -419,15 +419,25 @@ int gw_sigma_c(void* stream, const gw_sigma_desc* d_host, void* ws, size_t ws_by
  *                         tiles; 2 (default): 256 x 128 output tiles with the
  *                         staging of the next K stage interleaved with the
  *                         MFMAs.
- *   "gemm_staging"        pipeline 2 only: 1: 4 waves, operand stages pass
- *                         through registers into LDS; 2: 4 waves, direct
- *                         global-to-LDS copies; 3 (default): 8 waves (two per
- *                         SIMD), register staging; 4: 8 waves in ping-pong
- *                         (the two waves of a SIMD alternate between MFMAs
- *                         and memory work; same results bit for bit).
+ *   "gemm_staging"        pipeline 2 with complex_product 4: 1: 4 waves,
+ *                         operand stages pass through registers into LDS; 2:
+ *                         4 waves, direct global-to-LDS copies; 3 (default):
+ *                         8 waves (two per SIMD), register staging; 4: 8 waves
+ *                         in ping-pong (the two waves of a SIMD alternate
+ *                         between MFMAs and memory work; same results bit for
+ *                         bit).
+ *   "complex_product"     pipeline 2: 3 (default): every complex product of
+ *                         the projection and the accumulation as three real
+ *                         products (Gauss: T1 = ac, T2 = bd, T3 = (a+b)(c+d);
+ *                         Re = T1 - T2, Im = T3 - T1 - T2) on real operand
+ *                         planes, 8 waves, operands copied straight into LDS,
+ *                         a quarter fewer MFMAs; 4: four real products per
+ *                         complex product (the gemm_staging variants above).
  * Values out of range and unknown keys give GW_ERR_INVALID_ARG.  Not
- * thread-safe: set before launching work. */
+ * thread-safe: set before launching work.  gw_get_tuning reads a key's
+ * current value. */
 int gw_set_tuning(const char* key_host, int value);
+int gw_get_tuning(const char* key_host, int* value_host);
 
 /* ------------------------------------------------------------------ profiling
  * Optional per-kernel timing with HIP events recorded on the caller's stream

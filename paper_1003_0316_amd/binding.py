@@ -131,6 +131,7 @@ _lib.gw_polarization_learned_workspace_size.argtypes = [ctypes.POINTER(GwPolDesc
 _lib.gw_polarization_learned.argtypes = [_vp, ctypes.POINTER(GwPolDesc), _pl, _vp, _sz]
 
 _lib.gw_set_tuning.argtypes = [ctypes.c_char_p, _ci]
+_lib.gw_get_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(_ci)]
 _lib.gw_profile_enable.argtypes = [_ci]
 _lib.gw_profile_reset.argtypes = []
 _lib.gw_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(_ci), ctypes.POINTER(ctypes.c_double)]
@@ -148,7 +149,7 @@ EXPORTED = ("gw_last_error", "gw_version", "gw_project_workspace_size", "gw_proj
             "gw_profile_enable", "gw_profile_reset", "gw_profile_query",
             "gw_mlp_sizes", "gw_mlp_sync_bf16", "gw_mlp_forward", "gw_mlp_loss", "gw_mlp_workspace_size",
             "gw_mlp_backward", "gw_mlp_adam_step", "gw_surrogate_workspace_size", "gw_surrogate_features",
-            "gw_surrogate_targets", "gw_surrogate_apply", "gw_surrogate_judge", "gw_set_tuning",
+            "gw_surrogate_targets", "gw_surrogate_apply", "gw_surrogate_judge", "gw_set_tuning", "gw_get_tuning",
             "gw_sigma_c_workspace_size", "gw_sigma_c", "gw_basis_select_count", "gw_basis_select")
 
 
@@ -583,6 +584,12 @@ def gw_surrogate_judge(args: SurrogateArgs, Y, ldy, P_sample, sample_rows, strea
                                    os_.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), err.data_ptr(), ws.data_ptr(),
                                    ws.numel()))
     return err
+
+
+def gw_get_tuning(key: str) -> int:
+    v = ctypes.c_int(0)
+    _check(_lib.gw_get_tuning(key.encode(), ctypes.byref(v)))
+    return v.value
 
 
 def gw_set_tuning(key: str, value: int) -> None:

@@ -18,6 +18,7 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
 // Split-BF16 on pre-tiled operands (k_tiled.hip).
 extern int g_bf16_pipeline;   // 1: operands staged inside the GEMM kernels; 2: pre-tiled operands
 extern int g_gemm_staging;    // pre-tiled GEMM core: 1 through registers, 2 direct global -> LDS
+extern int g_complex_product; // pre-tiled pipeline: 4 real products per complex product, or 3 (Gauss form)
 size_t tiled_pol_workspace(int N, int R, int tc, int n_omega);
 size_t tiled_project_workspace(int N, int R, int T);
 int tiled_default_chunk_pairs(int N, int R, int n_omega);

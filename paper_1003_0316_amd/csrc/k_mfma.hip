@@ -1015,6 +1015,7 @@ int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32
 // so that the projection's workgroups fill whole rounds of the 256 CUs.
 int g_bf16_pipeline = 2;
 int g_gemm_staging = 3;
+int g_complex_product = 3;
 
 int mfma_default_chunk_pairs(int N, int R, int n_omega, int precision) {
   if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_default_chunk_pairs(N, R, n_omega);
@@ -1153,6 +1154,17 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
 
 }  // namespace gw
 
+extern "C" int gw_get_tuning(const char* key, int* value) {
+  if (!key || !value) return gw::fail(GW_ERR_INVALID_ARG, "gw_get_tuning: key and value are required");
+  const std::string k(key);
+  if (k == "projection_variant") *value = gw::g_proj_variant;
+  else if (k == "gemm_staging") *value = gw::g_gemm_staging;
+  else if (k == "bf16_pipeline") *value = gw::g_bf16_pipeline;
+  else if (k == "complex_product") *value = gw::g_complex_product;
+  else return gw::fail(GW_ERR_INVALID_ARG, std::string("gw_get_tuning: unknown key ") + key);
+  return GW_OK;
+}
+
 extern "C" int gw_set_tuning(const char* key, int value) {
   if (!key) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: key is NULL");
   const std::string k(key);
@@ -1164,6 +1176,11 @@ extern "C" int gw_set_tuning(const char* key, int value) {
   if (k == "gemm_staging") {
     if (value < 1 || value > 4) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: gemm_staging is 1 to 4");
     gw::g_gemm_staging = value;
+    return GW_OK;
+  }
+  if (k == "complex_product") {
+    if (value != 3 && value != 4) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: complex_product is 3 or 4");
+    gw::g_complex_product = value;
     return GW_OK;
   }
   if (k == "bf16_pipeline") {

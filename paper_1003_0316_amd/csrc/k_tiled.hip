@@ -62,6 +62,29 @@ __device__ inline void split2(float x, float& h, float& l) {
 }
 __device__ inline int lane_off(int sh, int row) { return (sh * TR + row) * 4; }
 
+// Three-multiplication form of the complex products (Gauss): with real planes
+// a = re, b = im of one operand and c, d of the other,
+//   T1 = sum a c,  T2 = sum b d,  T3 = sum (a + b)(c + d)   (projection)
+//   Re = T1 - T2,  Im = T3 - T1 - T2,
+// and for the accumulation's x conj(y) the second operand enters as (c, d,
+// c - d), giving Re = T1 + T2, Im = T3 - T1 + T2: three real products per
+// complex product instead of four.  Operands are real planes, one "plane word"
+// per block-stage holds 128 rows x 16 real values (4 KB): dword
+// (h * 128 + row) * 4 + j packs k = 8 h + 2 j and 8 h + 2 j + 1 (low, high
+// half), so the 32x32x16 MFMA fragment of lane (row = l % 32, h = l / 32) is
+// one aligned 16-byte vector.  Every plane is split hi + lo as above.
+constexpr int HWD = TR * 8;           // dwords per plane word per block-stage (1024 = 4 KB)
+__device__ inline int lane_off3(int h, int row) { return (h * TR + row) * 4; }
+
+// 8 values -> hi and lo plane-word vectors.
+__device__ inline void pack_plane(const float (&v)[8], uint4& hi, uint4& lo) {
+  float h[8], l[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) split2(v[q], h[q], l[q]);
+  hi = make_uint4(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]), pack_bf16(h[4], h[5]), pack_bf16(h[6], h[7]));
+  lo = make_uint4(pack_bf16(l[0], l[1]), pack_bf16(l[2], l[3]), pack_bf16(l[4], l[5]), pack_bf16(l[6], l[7]));
+}
+
 // ------------------------------------------------------------ operand tiling
 
 // U (c64 [N][R]) -> A-side words [nI][nst][4][WD]: conj(U) hi, lo, swap(U) hi, lo.
@@ -230,6 +253,171 @@ __global__ void scale_split_kernel(int nI, int nIe, int nstT, int Tp, int n_omeg
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         *reinterpret_cast<uint4*>(oj + (size_t)q * WD) = make_uint4(w[q][0], w[q][1], w[q][2], w[q][3]);
+    }
+  }
+}
+
+// ---- operands of the three-multiplication form
+// U (c64 [N][R]) -> plane words [nI][nst][6][HWD]: re hi, lo, im hi, lo,
+// (re + im) hi, lo.  Rows >= N and k >= R are zero.
+__global__ void tile_u3_kernel(int N, int R, int nI, int nst, const float2* __restrict__ U,
+                               uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nI * nst * 2 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % TR);
+    const int h = (int)((e / TR) % 2);
+    const size_t bs = e / (2 * TR);
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int I = blk * TR + row;
+    const int r0 = st * TK + 8 * h;
+    float re[8], im[8], sm[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float2 x = make_float2(0.f, 0.f);
+      if (I < N && r0 + q < R) x = U[(size_t)I * R + r0 + q];
+      re[q] = x.x;
+      im[q] = x.y;
+      sm[q] = x.x + x.y;
+    }
+    uint32_t* o = out + bs * 6 * HWD + lane_off3(h, row);
+    uint4 hi, lo;
+    pack_plane(re, hi, lo);
+    *reinterpret_cast<uint4*>(o) = hi;
+    *reinterpret_cast<uint4*>(o + HWD) = lo;
+    pack_plane(im, hi, lo);
+    *reinterpret_cast<uint4*>(o + 2 * HWD) = hi;
+    *reinterpret_cast<uint4*>(o + 3 * HWD) = lo;
+    pack_plane(sm, hi, lo);
+    *reinterpret_cast<uint4*>(o + 4 * HWD) = hi;
+    *reinterpret_cast<uint4*>(o + 5 * HWD) = lo;
+  }
+}
+
+// Pair products F_t = conj(psi_occ) psi_unocc of one chunk -> plane words
+// [nT][nst][6][HWD] (re, im, re + im; hi, lo), pairs t >= T and k >= R zero.
+// Same two phases as pair_product_kernel: rows read as 256-byte segments into
+// an LDS tile, then lane = pair, 8 k per item, 1 KB per store.
+__global__ __launch_bounds__(256) void pair_product3_kernel(int R, int nst, int nT, const float2* __restrict__ po,
+                                                            const float2* __restrict__ pu, int nu, long tb, int T,
+                                                            uint32_t* __restrict__ out) {
+  __shared__ float2 F[TR * PP_PITCH];
+  const int blk = blockIdx.y;
+  const int st0 = blockIdx.x * 2;
+  const int tid = threadIdx.x;
+  const int r0 = st0 * TK;
+  const int sub = tid & 15, prow = tid >> 4;
+#pragma unroll
+  for (int pass = 0; pass < TR / 16; ++pass) {
+    const int p = pass * 16 + prow;
+    const int t = blk * TR + p;
+    const int r = r0 + 2 * sub;
+    float2 f0 = make_float2(0.f, 0.f), f1 = make_float2(0.f, 0.f);
+    if (t < T) {
+      const long g = tb + t;
+      const float2* a = po + (size_t)(g / nu) * R;
+      const float2* b = pu + (size_t)(g % nu) * R;
+      float2 x0 = make_float2(0.f, 0.f), x1 = x0, y0 = x0, y1 = x0;
+      if (r + 1 < R && ((R & 1) == 0)) {
+        const float4 xa = *reinterpret_cast<const float4*>(a + r);
+        const float4 yb = *reinterpret_cast<const float4*>(b + r);
+        x0 = make_float2(xa.x, xa.y); x1 = make_float2(xa.z, xa.w);
+        y0 = make_float2(yb.x, yb.y); y1 = make_float2(yb.z, yb.w);
+      } else {
+        if (r < R) { x0 = a[r]; y0 = b[r]; }
+        if (r + 1 < R) { x1 = a[r + 1]; y1 = b[r + 1]; }
+      }
+      f0 = make_float2(x0.x * y0.x + x0.y * y0.y, x0.x * y0.y - x0.y * y0.x);
+      f1 = make_float2(x1.x * y1.x + x1.y * y1.y, x1.x * y1.y - x1.y * y1.x);
+    }
+    F[p * PP_PITCH + 2 * sub] = f0;
+    F[p * PP_PITCH + 2 * sub + 1] = f1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < (TR * PP_K / 8) / 256; ++it) {
+    const int item = it * 256 + tid;
+    const int p = item & (TR - 1), grp = item >> 7;   // grp: 0..3 (stage = grp / 2, h = grp % 2)
+    float re[8], im[8], sm[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float2 f = F[p * PP_PITCH + grp * 8 + q];
+      re[q] = f.x;
+      im[q] = f.y;
+      sm[q] = f.x + f.y;
+    }
+    const int st = st0 + (grp >> 1);
+    if (st < nst) {
+      uint32_t* o = out + ((size_t)blk * nst + st) * 6 * HWD + lane_off3(grp & 1, p);
+      uint4 hi, lo;
+      pack_plane(re, hi, lo);
+      *reinterpret_cast<uint4*>(o) = hi;
+      *reinterpret_cast<uint4*>(o + HWD) = lo;
+      pack_plane(im, hi, lo);
+      *reinterpret_cast<uint4*>(o + 2 * HWD) = hi;
+      *reinterpret_cast<uint4*>(o + 3 * HWD) = lo;
+      pack_plane(sm, hi, lo);
+      *reinterpret_cast<uint4*>(o + 4 * HWD) = hi;
+      *reinterpret_cast<uint4*>(o + 5 * HWD) = lo;
+    }
+  }
+}
+
+// M (tiled complex FP32, as written by the projection) -> X_j = s_j M as plane
+// words [n_omega][nIe][nstT][8][HWD]: a = re x, b = im x, a + b, a - b (hi,
+// lo each); the accumulation reads planes 0..5 as its first operand and
+// planes 0..3, 6, 7 as the second.  Blocks in [nI, nIe) are zero.
+__global__ void scale_split3_kernel(int nI, int nIe, int nstT, int Tp, int n_omega, const float2* __restrict__ Mt,
+                                    const float* __restrict__ sw, uint32_t* __restrict__ X) {
+  const size_t total = (size_t)nIe * nstT * 2 * TR;
+  const size_t xstride = (size_t)nIe * nstT * 8 * HWD;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % TR);
+    const int h = (int)((e / TR) % 2);
+    const size_t bs = e / (2 * TR);
+    const int st = (int)(bs % nstT), blk = (int)(bs / nstT);
+    float2 m[8];
+    if (blk < nI) {
+#pragma unroll
+      for (int g2 = 0; g2 < 2; ++g2) {
+        const float4* src = reinterpret_cast<const float4*>(Mt + ((bs * 4 + 2 * h + g2) * TR + row) * 4);
+        const float4 p = src[0], q = src[1];
+        m[4 * g2 + 0] = make_float2(p.x, p.y);
+        m[4 * g2 + 1] = make_float2(p.z, p.w);
+        m[4 * g2 + 2] = make_float2(q.x, q.y);
+        m[4 * g2 + 3] = make_float2(q.z, q.w);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) m[q] = make_float2(0.f, 0.f);
+    }
+    const int t0 = st * TK + 8 * h;
+    uint32_t* o = X + bs * 8 * HWD + lane_off3(h, row);
+    for (int jw = 0; jw < n_omega; ++jw) {
+      const float4 s0 = *reinterpret_cast<const float4*>(sw + (size_t)jw * Tp + t0);
+      const float4 s1 = *reinterpret_cast<const float4*>(sw + (size_t)jw * Tp + t0 + 4);
+      const float sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+      float a[8], b[8], ps[8], ms[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a[q] = sv[q] * m[q].x;
+        b[q] = sv[q] * m[q].y;
+        ps[q] = a[q] + b[q];
+        ms[q] = a[q] - b[q];
+      }
+      uint32_t* oj = o + (size_t)jw * xstride;
+      uint4 hi, lo;
+      pack_plane(a, hi, lo);
+      *reinterpret_cast<uint4*>(oj) = hi;
+      *reinterpret_cast<uint4*>(oj + HWD) = lo;
+      pack_plane(b, hi, lo);
+      *reinterpret_cast<uint4*>(oj + 2 * HWD) = hi;
+      *reinterpret_cast<uint4*>(oj + 3 * HWD) = lo;
+      pack_plane(ps, hi, lo);
+      *reinterpret_cast<uint4*>(oj + 4 * HWD) = hi;
+      *reinterpret_cast<uint4*>(oj + 5 * HWD) = lo;
+      pack_plane(ms, hi, lo);
+      *reinterpret_cast<uint4*>(oj + 6 * HWD) = hi;
+      *reinterpret_cast<uint4*>(oj + 7 * HWD) = lo;
     }
   }
 }
@@ -491,6 +679,11 @@ struct GemmArgs {
   long ldm;
   int nst_out;
   double2* P;          // OUT_HERK: n_omega x [N][N]
+  // three-multiplication core only: plane words per block-stage of A and B,
+  // the plane of B holding c + d (projection) or c - d (accumulation), and
+  // the sign s of Re = T1 + s T2, Im = T3 - T1 + s T2
+  int a_words3, b_words3, b_sum3;
+  float sigma3;
 };
 
 __device__ inline floatx16 mma(uint4 a, uint4 b, floatx16 c) {
@@ -1162,6 +1355,153 @@ __global__ __launch_bounds__(GT8, 1) void gemm8pp_bf16x3_kernel(GemmArgs g) {
       }
 }
 
+// ------------------------------------- three-multiplication core (Gauss form)
+// Tile 128 x 256, 8 waves of 64 x 64 outputs, K stage = 16 complex k.  Each
+// stage holds, per operand row, the hi and lo plane words of three real
+// planes (A: 24 KB, B: two 128-column halves of 24 KB), copied straight from
+// the tiled arrays into LDS (global_load_lds, no staging registers: the
+// 192 accumulators of T1, T2, T3 leave no room for them), double-buffered
+// (144 KB).  Per stage and wave: for each plane, 4 A and 4 B fragments and 12
+// MFMAs (hi hi, hi lo, lo hi) -- 36 MFMAs and 24 LDS reads for 16 complex k,
+// against 48 MFMAs and 24 reads in the four-product core.
+constexpr int ST3 = 18 * HWD;                                    // dwords per LDS stage
+constexpr size_t kGemm3Lds = 2 * (size_t)ST3 * sizeof(uint32_t); // 144 KB
+
+// DMA of stage st into LDS buffer L: 72 chunks of 1 KB (A plane words 0..5,
+// then the two B halves' plane words), chunk q by wave q % 8.
+__device__ __forceinline__ void stage_dma3(uint32_t* L, const GemmArgs& g, const uint32_t* Ap, const uint32_t* B0,
+                                           const uint32_t* B1, int st, int w, int lane) {
+  const size_t a_step = (size_t)g.a_words3 * HWD, b_step = (size_t)g.b_words3 * HWD;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int q = w + 8 * i;                 // wave-uniform
+    const int region = q / 24, r = q % 24, pw = r >> 2, sub = r & 3;
+    const uint32_t* src;
+    if (region == 0) {
+      src = Ap + (size_t)st * a_step + (size_t)pw * HWD;
+    } else {
+      const uint32_t* Bb = region == 1 ? B0 : B1;
+      const int plane = pw < 4 ? pw : g.b_sum3 + (pw - 4);
+      src = Bb + (size_t)st * b_step + (size_t)plane * HWD;
+    }
+    __builtin_amdgcn_global_load_lds(src + sub * 256 + lane * 4, (lds_void*)(L + q * 256), 16, 0, 0);
+  }
+}
+
+template <int OUT>
+__global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  int ti, tj, jw;
+  decode_tile<OUT>(g, ti, tj, jw);
+  const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
+  const uint32_t* B0 = g.B + jw * g.omega_stride + (size_t)(2 * tj) * g.b_bstride;
+  const uint32_t* B1 = B0 + g.b_bstride;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w >> 2, wn = w & 3;
+  const int half = wn >> 1, c0 = (wn & 1) * 64;
+  const int l32 = lane & 31, h = lane >> 5;
+
+  floatx16 t[3][2][2];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) t[p][a][b][v] = 0.f;
+
+  const int aoff = lane_off3(h, wm * 64 + l32);
+  const int boff = (6 + 6 * half) * HWD + lane_off3(h, c0 + l32);
+  stage_dma3(lds, g, Ap, B0, B1, 0, w, lane);
+  for (int st = 0; st < g.nst; ++st) {
+    wait_vm0();
+    lds_barrier();
+    if (st + 1 < g.nst) stage_dma3(lds + ((st + 1) & 1) * ST3, g, Ap, B0, B1, st + 1, w, lane);
+    const uint32_t* L = lds + (st & 1) * ST3;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      uint4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        ah[rb] = *reinterpret_cast<const uint4*>(L + (2 * p) * HWD + aoff + rb * 128);
+        al[rb] = *reinterpret_cast<const uint4*>(L + (2 * p + 1) * HWD + aoff + rb * 128);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        bh[cb] = *reinterpret_cast<const uint4*>(L + boff + (2 * p) * HWD + cb * 128);
+        bl[cb] = *reinterpret_cast<const uint4*>(L + boff + (2 * p + 1) * HWD + cb * 128);
+      }
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          t[p][rb][cb] = mma(ah[rb], bh[cb], t[p][rb][cb]);
+          t[p][rb][cb] = mma(ah[rb], bl[cb], t[p][rb][cb]);
+          t[p][rb][cb] = mma(al[rb], bh[cb], t[p][rb][cb]);
+        }
+    }
+  }
+  __syncthreads();   // every wave is done with the last stage's LDS
+
+  const float sg = g.sigma3;
+  if constexpr (OUT == OUT_HERK) {
+    float2* E = reinterpret_cast<float2*>(lds);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (half == c) {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+              const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
+              E[row * 128 + c0 + cb * 32 + l32] = make_float2(t1 + sg * t2, t3 - t1 + sg * t2);
+            }
+      }
+      __syncthreads();
+      double2* Pj = g.P + (size_t)jw * g.N * g.N;
+#pragma unroll 4
+      for (int e = tid; e < 128 * 128; e += GT8) {
+        const int gi = ti * TM + (e >> 7), gj = tj * TN + c * 128 + (e & 127);
+        if (gi < g.N && gj <= gi) {
+          const float2 x = E[e];
+          double2* pp = Pj + (size_t)gi * g.N + gj;
+          double2 y = *pp;
+          y.x -= (double)x.x;
+          y.y -= (double)x.y;
+          *pp = y;
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * 64 + cb * 32 + l32;
+        const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
+        const float re = t1 + sg * t2, im = t3 - t1 + sg * t2;
+        if constexpr (OUT == OUT_TILED) {
+          const int tt = tj * TN + col;
+          const size_t bs = (size_t)ti * g.nst_out + tt / TK;
+          const int kk = tt % TK;
+          g.M[(bs * 4 + (kk >> 2)) * TR * 4 + row * 4 + (kk & 3)] = make_float2(re, im);
+        } else {
+          const int gi = ti * TM + row, gt = tj * TN + col;
+          if (gi < g.N && gt < g.T) g.M[(size_t)gi * g.ldm + gt] = make_float2(re, im);
+        }
+      }
+}
+
 template <int OUT>
 int launch_gemm8pp(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
   static int attr = 0;
@@ -1200,6 +1540,7 @@ int count_lower_tiles(int nI) {
 struct TiledDims {
   int nI, nIe, nstR, Tp, nT, nstT;
   size_t u_words, q_words, m_c64, x_words, sw_f32;
+  size_t u3_words, q3_words, x3_words;   // the three-multiplication core's plane words
   TiledDims(int N, int R, int T, int n_omega) {
     nI = cdiv(N, TR);
     nIe = (nI + 1) & ~1;
@@ -1212,6 +1553,13 @@ struct TiledDims {
     m_c64 = (size_t)nI * nstT * WD;
     x_words = (size_t)n_omega * nIe * nstT * 4 * WD;
     sw_f32 = (size_t)n_omega * Tp;
+    u3_words = (size_t)nI * nstR * 6 * HWD;
+    q3_words = (size_t)nT * nstR * 6 * HWD;
+    x3_words = (size_t)n_omega * nIe * nstT * 8 * HWD;
+    // one workspace layout serves both cores (the larger of each array)
+    u_words = std::max(u_words, u3_words);
+    q_words = std::max(q_words, q3_words);
+    x_words = std::max(x_words, x3_words);
   }
   size_t bytes() const {
     return align_up(u_words * 4) + align_up(q_words * 4) + align_up(m_c64 * 8) + align_up(x_words * 4) +
@@ -1261,10 +1609,58 @@ int launch_gemm8(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
 }
 
 template <int OUT>
+int launch_gemm3m(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
+  static int attr = 0;
+  if (!attr) {
+    GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm3m_kernel<OUT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemm3Lds));
+    attr = 1;
+  }
+  ProfScope prof(s, name);
+  hipLaunchKernelGGL((gemm3m_kernel<OUT>), dim3(grid), dim3(GT8), kGemm3Lds, s, a);
+  GW_LAUNCHED("gemm3m_kernel");
+  return GW_OK;
+}
+
+template <int OUT>
 int launch_gemm(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
   if (g_gemm_staging == 4) return launch_gemm8pp<OUT>(s, a, grid, name);
   if (g_gemm_staging == 3) return launch_gemm8<OUT>(s, a, grid, name);
   return g_gemm_staging == 2 ? launch_gemm_as<OUT, 1>(s, a, grid, name) : launch_gemm_as<OUT, 0>(s, a, grid, name);
+}
+
+int launch_tile_u3(hipStream_t s, const TiledDims& d, int N, int R, const float2* U, uint32_t* Uw) {
+  hipLaunchKernelGGL(tile_u3_kernel, dim3(stream_blocks((size_t)d.nI * d.nstR * 2 * TR)), dim3(256), 0, s, N, R,
+                     d.nI, d.nstR, U, Uw);
+  GW_LAUNCHED("tile_u3_kernel");
+  return GW_OK;
+}
+
+int launch_pair_product3(hipStream_t s, const TiledDims& d, int R, const float2* po, const float2* pu, int nu, long tb,
+                         int T, uint32_t* Q) {
+  ProfScope prof(s, "pair_product_kernel");
+  hipLaunchKernelGGL(pair_product3_kernel, dim3((d.nstR + 1) / 2, d.nT), dim3(256), 0, s, R, d.nstR, d.nT, po, pu,
+                     nu, tb, T, Q);
+  GW_LAUNCHED("pair_product3_kernel");
+  return GW_OK;
+}
+
+// Projection arguments of the three-multiplication core: A = U planes, B =
+// product planes (re, im, re + im).
+void set_projection3(GemmArgs& a, const TiledDims& d, const uint32_t* Uw, const uint32_t* Q, int N, int T) {
+  a.A = Uw;
+  a.B = Q;
+  a.a_words3 = 6;
+  a.b_words3 = 6;
+  a.b_sum3 = 4;
+  a.sigma3 = -1.f;
+  a.nst = d.nstR;
+  a.a_bstride = (size_t)d.nstR * 6 * HWD;
+  a.b_bstride = (size_t)d.nstR * 6 * HWD;
+  a.nI = d.nI;
+  a.nTj = d.Tp / TN;
+  a.N = N;
+  a.T = T;
 }
 
 }  // namespace
@@ -1304,6 +1700,15 @@ int tiled_project(hipStream_t s, int N, int R, int n_occ, int n_unocc, const flo
   uint32_t* Uw = cv.take<uint32_t>(d.u_words);
   uint32_t* Q = cv.take<uint32_t>(d.q_words);
   int st;
+  if (g_complex_product == 3) {
+    if ((st = launch_tile_u3(s, d, N, R, U, Uw)) != GW_OK) return st;
+    if ((st = launch_pair_product3(s, d, R, po, pu, n_unocc, 0, T, Q)) != GW_OK) return st;
+    GemmArgs a{};
+    set_projection3(a, d, Uw, Q, N, T);
+    a.M = M;
+    a.ldm = T;
+    return launch_gemm3m<OUT_ROWS>(s, a, d.nI * a.nTj, "project_rows_bf16_kernel");
+  }
   if ((st = launch_tile_u(s, d, N, R, U, Uw)) != GW_OK) return st;
   if ((st = launch_pair_product(s, d, R, po, pu, n_unocc, 0, T, Q)) != GW_OK) return st;
   GemmArgs a{};
@@ -1334,8 +1739,48 @@ int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Ch
   const float2* psi = static_cast<const float2*>(d.psi);
   const int nb = d.n_occ + d.n_unocc;
   int st;
-  if ((st = launch_tile_u(s, dm, d.N, d.R, static_cast<const float2*>(d.U), Uw)) != GW_OK) return st;
   const int n_tiles = count_lower_tiles(dm.nI);
+  if (g_complex_product == 3) {
+    if ((st = launch_tile_u3(s, dm, d.N, d.R, static_cast<const float2*>(d.U), Uw)) != GW_OK) return st;
+    for (const Chunk& c : chunks) {
+      TiledDims cd(d.N, d.R, c.T, d.n_omega);
+      const float2* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
+      const float2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
+      hipLaunchKernelGGL(weights_sqrt_kernel, dim3(cdiv(cd.Tp, 256)), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om,
+                         cd.Tp, sw);
+      GW_LAUNCHED("weights_sqrt_kernel");
+      if ((st = launch_pair_product3(s, cd, d.R, po, pu, c.nu, c.tb, c.T, Q)) != GW_OK) return st;
+      GemmArgs a{};
+      set_projection3(a, cd, Uw, Q, d.N, c.T);
+      a.M = Mt;
+      a.nst_out = cd.nstT;
+      if ((st = launch_gemm3m<OUT_TILED>(s, a, cd.nI * a.nTj, "project_bf16_kernel")) != GW_OK) return st;
+      {
+        ProfScope prof(s, "scale_split_kernel");
+        hipLaunchKernelGGL(scale_split3_kernel, dim3(stream_blocks((size_t)cd.nIe * cd.nstT * 2 * TR)), dim3(256), 0,
+                           s, cd.nI, cd.nIe, cd.nstT, cd.Tp, d.n_omega, Mt, sw, X);
+        GW_LAUNCHED("scale_split3_kernel");
+      }
+      GemmArgs b{};
+      b.A = X;
+      b.B = X;
+      b.a_words3 = 8;
+      b.b_words3 = 8;
+      b.b_sum3 = 6;
+      b.sigma3 = 1.f;
+      b.nst = cd.nstT;
+      b.a_bstride = (size_t)cd.nstT * 8 * HWD;
+      b.b_bstride = (size_t)cd.nstT * 8 * HWD;
+      b.omega_stride = (size_t)cd.nIe * cd.nstT * 8 * HWD;
+      b.nI = cd.nI;
+      b.n_tiles = n_tiles;
+      b.N = d.N;
+      b.P = reinterpret_cast<double2*>(d.P);
+      if ((st = launch_gemm3m<OUT_HERK>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")) != GW_OK) return st;
+    }
+    return GW_OK;
+  }
+  if ((st = launch_tile_u(s, dm, d.N, d.R, static_cast<const float2*>(d.U), Uw)) != GW_OK) return st;
   for (const Chunk& c : chunks) {
     // the chunk arrays are sized for tc pairs; a shorter last chunk pads with zeros
     TiledDims cd(d.N, d.R, c.T, d.n_omega);

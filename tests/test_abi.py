@@ -150,7 +150,8 @@ def test_tuning_switches_validate(b):
     """gw_set_tuning accepts the documented keys and values only (host-side)."""
     L = b.lib()
     for key, lo, hi, default in (("bf16_pipeline", 1, 2, 2), ("projection_variant", 1, 2, 2),
-                                 ("gemm_staging", 1, 4, 3)):
+                                 ("gemm_staging", 1, 4, 3), ("complex_product", 3, 4, 3)):
+        assert b.gw_get_tuning(key) == default
         for v in (lo, hi):
             assert L.gw_set_tuning(key.encode(), v) == 0
         for v in (lo - 1, hi + 1):
@@ -159,6 +160,8 @@ def test_tuning_switches_validate(b):
         assert L.gw_set_tuning(key.encode(), default) == 0
     assert L.gw_set_tuning(b"no_such_key", 1) == -1
     assert L.gw_set_tuning(None, 1) == -1
+    v = ctypes.c_int(0)
+    assert L.gw_get_tuning(b"no_such_key", ctypes.byref(v)) == -1
 
 
 def _sigma_desc(b, **over):

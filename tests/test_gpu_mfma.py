@@ -145,6 +145,7 @@ def test_split_bf16_kernel_variants(lib, pipeline, pv, staging):
     inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=9, omega=gwsynth.omega_mesh("m16"))
     U, psi = _dev(inp)
     try:
+        lib.gw_set_tuning("complex_product", 4)
         lib.gw_set_tuning("bf16_pipeline", pipeline)
         lib.gw_set_tuning("projection_variant", pv)
         lib.gw_set_tuning("gemm_staging", staging)
@@ -152,6 +153,7 @@ def test_split_bf16_kernel_variants(lib, pipeline, pv, staging):
         M = lib.gw_project(U, psi[0, :3].contiguous(), psi[0, 3:].contiguous(), "split_bf16")
         torch.cuda.synchronize()
     finally:
+        lib.gw_set_tuning("complex_product", 3)
         lib.gw_set_tuning("bf16_pipeline", 2)
         lib.gw_set_tuning("projection_variant", 2)
         lib.gw_set_tuning("gemm_staging", 3)
@@ -211,3 +213,40 @@ def test_single_fp16_ablation_misses_the_bar(lib):
     assert 5e-5 < em < 2e-3
     for j in range(P1.shape[0]):
         assert np.array_equal(P1[j], P1[j].conj().T)
+
+
+@pytest.mark.parametrize("shape", [
+    dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150),
+    dict(n_k=1, n_b=20, R=33, N=7, n_occ=1, n_unocc=5),
+    dict(n_k=3, n_b=64, R=512, N=129, n_occ=2, n_unocc=63),
+])
+def test_three_product_core(lib, shape):
+    """The three-multiplication (Gauss) form of the GEMM core (complex_product
+    3, the default): polarization (projection and accumulation) and row-major projections
+    on ragged multi-tile shapes, within the reduced-precision bar; P
+    Hermitian; the judge's row projections in the learned path use it too."""
+    import torch
+    inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=9, omega=gwsynth.omega_mesh("m16"))
+    U, psi = _dev(inp)
+    n_occ = shape["n_occ"]
+    try:
+        lib.gw_set_tuning("complex_product", 3)
+        P = lib.gw_polarization(U, psi, inp.eps, inp.omega, n_occ, precision="split_bf16", kq=inp.kq)
+        M = lib.gw_project(U, psi[0, :n_occ].contiguous(), psi[0, n_occ:].contiguous(), "split_bf16")
+        Pc = lib.gw_polarization(U, psi, inp.eps, inp.omega, n_occ, precision="split_bf16", kq=inp.kq,
+                                 chunk_pairs=256)
+        torch.cuda.synchronize()
+    finally:
+        lib.gw_set_tuning("complex_product", 3)
+    Ur, pr = _rounded(inp)
+    ref = orc.polarization(Ur, pr, inp.eps, inp.omega, n_occ, kq=inp.kq)
+    Pg = P.cpu().numpy()
+    err = orc.rel_fro(Pg, ref)
+    errc = orc.rel_fro(Pc.cpu().numpy(), ref)
+    Mref = orc.projections(Ur, pr[0, :n_occ], pr[0, n_occ:])
+    merr = np.linalg.norm(M.cpu().numpy() - Mref) / np.linalg.norm(Mref)
+    print(f"three-product core {shape}: P max rel err {err.max():.2e} (chunked {errc.max():.2e}), M {merr:.2e}")
+    assert err.max() < TOL and errc.max() < TOL
+    assert merr < 2e-5
+    for j in range(Pg.shape[0]):
+        assert np.array_equal(Pg[j], Pg[j].conj().T)
