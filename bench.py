@@ -63,9 +63,6 @@ def parse():
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv outputs (bench run, then the copy "
                          "calibration) into the traffic file")
-    ap.add_argument("--traffic-driver", action="store_true",
-                    help="only run the main explicit-band polarization of one k-point on Gaussian inputs of the "
-                         "workload's shape (no device QR; the launch sequence for HBM traffic counters)")
     ap.add_argument("--sigma", action="store_true",
                     help="measure the correlation self-energy instead (supercell workload: W for every momentum "
                          "transfer, then Sigma_c(i w) of the highest occupied and lowest unoccupied state)")
@@ -106,37 +103,6 @@ def copy_calibration() -> int:
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": n, "copies": 3}))
-    return 0
-
-
-def traffic_driver(a) -> int:
-    """One k-point of the bench's explicit-band polarization (same N, R,
-    occupied bands, cutoff, frequencies and chunking) on unorthogonalised
-    Gaussian inputs: the projection / accumulation launches and their memory
-    traffic depend on the shapes only."""
-    import numpy as np
-    import torch
-
-    import gwsynth
-    from paper_1003_0316_amd import binding as gw
-    dev = torch.device("cuda:0")
-    shp = gwsynth.SHAPES[a.workload]
-    cutoff = a.cutoff or shp.n_unocc_cut or shp.n_unocc
-    g = torch.Generator(device=dev)
-    g.manual_seed(20100316)
-
-    def cgauss(*shape):
-        return torch.complex(torch.randn(*shape, device=dev, generator=g),
-                             torch.randn(*shape, device=dev, generator=g)) / np.sqrt(2.0 * shape[-1])
-    U = cgauss(shp.N, shp.R)
-    psi = cgauss(1, shp.n_occ + cutoff, shp.R)
-    rng = np.random.default_rng(20100316)
-    eps = np.concatenate([np.sort(rng.uniform(-0.5, 0.0, shp.n_occ)), np.sort(rng.uniform(0.02, 2.0, cutoff))])[None]
-    omega = gwsynth.omega_mesh("m16")
-    call = gw.PolarizationCall(U, psi, eps, omega, shp.n_occ, precision=a.precision, kq=[0])
-    call.run()
-    torch.cuda.synchronize()
-    print(json.dumps({"traffic_driver": a.workload, "pairs": shp.n_occ * cutoff, "precision": a.precision}))
     return 0
 
 
@@ -667,8 +633,6 @@ def main() -> int:
             key, _, value = kv.partition("=")
             gw.gw_set_tuning(key, int(value))
             log(f"tuning {key} = {int(value)}")
-    if a.traffic_driver:
-        return traffic_driver(a)
     if a.sigma:
         return sigma_bench(a)
     if a.real:
