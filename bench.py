@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-model-error", action="store_true",
                     help="skip the all-band reference pass (model error of the learned correction)")
     ap.add_argument("--sample-occ", type=int, default=2, help="judge sample: occupied bands per k-point")
+    ap.add_argument("--chunk-pairs", type=int, default=0, help="transition pairs per chunk (0: library default)")
     ap.add_argument("--judge-tol", type=float, default=0.25, help="judge tolerance of the learned correction")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time for cpu_baseline")
@@ -687,6 +688,7 @@ def main() -> int:
         surrogate = sg.Surrogate.load_default(dev, judge_tol=a.judge_tol)
         learned = surrogate.learned_call(U, psi, inp.eps, eps_dev, inp.omega, shp.n_occ, cutoff, inp.kq,
                                          precision=a.precision, n_sample_occ=n_sample_occ)
+        learned.pol.desc.chunk_pairs = a.chunk_pairs
         P = learned.pol.P
         ws = torch.empty(learned.workspace_size(), dtype=torch.uint8, device=dev)
 
@@ -695,7 +697,7 @@ def main() -> int:
             sur_report.update(rep)
     else:
         pol = gw.PolarizationCall(U, psi, inp.eps, inp.omega, shp.n_occ, precision=a.precision, eps_dev=eps_dev,
-                                  kq=inp.kq, unocc_range=(0, cutoff))
+                                  kq=inp.kq, unocc_range=(0, cutoff), chunk_pairs=a.chunk_pairs)
         P = pol.P
         ws = torch.empty(pol.workspace_size(), dtype=torch.uint8, device=dev)
 
@@ -997,7 +999,8 @@ def main() -> int:
                                        if learned_path else None),
                    "step": ("P (explicit bands, learned correction, judge sample) + W (FP64 screening)"
                             if learned_path else "P (all bands) + W (FP64 screening)"),
-                   **({"tuning": a.tuning} if a.tuning else {})},
+                   **({"tuning": a.tuning} if a.tuning else {}),
+                   **({"chunk_pairs": a.chunk_pairs} if a.chunk_pairs else {})},
         "pairs_per_step": {"explicit": T_main, "judge_sample_projected": T_sample},
         "kernels_s_per_step": breakdown,
         "roofline": roofline,

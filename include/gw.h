@@ -426,6 +426,14 @@ int gw_sigma_c(void* stream, const gw_sigma_desc* d_host, void* ws, size_t ws_by
  *                         in ping-pong (the two waves of a SIMD alternate
  *                         between MFMAs and memory work; same results bit for
  *                         bit).
+ *   "fp16_core"           GW_SPLIT_FP16: 1 (default): operands staged inside
+ *                         the GEMM kernels, lo words pre-scaled by 2^11 in a
+ *                         separate accumulator (FP32-level accuracy); 2: the
+ *                         three-multiplication core below on plane words with
+ *                         power-of-two row / pair scales (hi in [2^13, 2^14))
+ *                         and one accumulator set: twice as fast, the
+ *                         accuracy of split BF16 (the FP32 accumulation of the
+ *                         three products per accumulator dominates).
  *   "complex_product"     pipeline 2: 3 (default): every complex product of
  *                         the projection and the accumulation as three real
  *                         products (Gauss: T1 = ac, T2 = bd, T3 = (a+b)(c+d);

@@ -113,7 +113,8 @@ Plan make_plan_direct(const gw_pol_desc& d) {
     pl.ws = align_up((size_t)d.N * pl.tc * 16) + align_up((size_t)d.n_omega * pl.tc * sizeof(double));
   } else {
     pl.ws = d.real_inputs ? tiled_pol_workspace_real(d.N, d.R, pl.tc, d.n_omega)
-                          : mfma_pol_workspace(d.precision, d.N, d.R, pl.tc, d.n_omega);
+                          : mfma_pol_workspace(d.precision, d.N, d.R, pl.tc, d.n_omega,
+                                               (size_t)d.n_k * (d.n_occ + d.n_unocc));
   }
   return pl;
 }

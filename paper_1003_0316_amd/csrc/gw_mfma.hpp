@@ -8,7 +8,7 @@
 namespace gw {
 
 int mfma_default_chunk_pairs(int N, int R, int n_omega, int precision);
-size_t mfma_pol_workspace(int precision, int N, int R, int tc, int n_omega);
+size_t mfma_pol_workspace(int precision, int N, int R, int tc, int n_omega, size_t psi_rows);
 size_t mfma_project_workspace(int precision, int N, int R, int n_occ, int n_unocc);
 int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_unocc, const void* U,
                  const void* psi_occ, const void* psi_unocc, void* M, void* ws, size_t ws_bytes);
@@ -19,8 +19,14 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
 extern int g_bf16_pipeline;   // 1: operands staged inside the GEMM kernels; 2: pre-tiled operands
 extern int g_gemm_staging;    // pre-tiled GEMM core: 1 through registers, 2 direct global -> LDS
 extern int g_complex_product; // pre-tiled pipeline: 4 real products per complex product, or 3 (Gauss form)
-size_t tiled_pol_workspace(int N, int R, int tc, int n_omega);
-size_t tiled_project_workspace(int N, int R, int T);
+extern int g_fp16_core;       // split FP16: 1 operands staged inside the GEMM kernels, 2 the three-product core
+size_t tiled_pol_workspace(int N, int R, int tc, int n_omega, size_t psi_rows);
+size_t tiled_project_workspace(int N, int R, int n_occ, int n_unocc);
+// Split FP16 on the three-multiplication core (power-of-two scaled plane words).
+int tiled_polarization_f16(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
+                           const OmegaList& om, void* ws);
+int tiled_project_f16(hipStream_t s, int N, int R, int n_occ, int n_unocc, const float2* U, const float2* po,
+                      const float2* pu, float2* M, void* ws);
 int tiled_default_chunk_pairs(int N, int R, int n_omega);
 int tiled_project(hipStream_t s, int N, int R, int n_occ, int n_unocc, const float2* U, const float2* po,
                   const float2* pu, float2* M, void* ws);

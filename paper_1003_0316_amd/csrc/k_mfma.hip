@@ -1016,9 +1016,14 @@ int launch_project16(hipStream_t s, int word, int N, int R, int Rp, const uint32
 int g_bf16_pipeline = 2;
 int g_gemm_staging = 3;
 int g_complex_product = 3;
+int g_fp16_core = 1;
+
+static bool tiled_path(int precision) {
+  return (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) || (precision == GW_SPLIT_FP16 && g_fp16_core == 2);
+}
 
 int mfma_default_chunk_pairs(int N, int R, int n_omega, int precision) {
-  if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_default_chunk_pairs(N, R, n_omega);
+  if (tiled_path(precision)) return tiled_default_chunk_pairs(N, R, n_omega);
   const int tile_rows = (precision == GW_SPLIT_BF16 && g_proj_variant == 2 && N >= kLargeTileN) ? BM2 : BM;
   const long rows = (N + tile_rows - 1) / tile_rows;
   const long cap = std::max<long>(1, std::min<long>(64, (256L << 20) / ((long)N * 8 * BN)));
@@ -1042,14 +1047,14 @@ static size_t split_u_bytes(int precision, int N, int R) {
   return 2 * align_up((size_t)N * Rp * sizeof(uint32_t)) + align_up(sizeof(Scales));
 }
 
-size_t mfma_pol_workspace(int precision, int N, int R, int tc, int n_omega) {
-  if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_pol_workspace(N, R, tc, n_omega);
+size_t mfma_pol_workspace(int precision, int N, int R, int tc, int n_omega, size_t psi_rows) {
+  if (tiled_path(precision)) return tiled_pol_workspace(N, R, tc, n_omega, psi_rows);
   return split_u_bytes(precision, N, R) + align_up((size_t)N * tc * sizeof(float2)) +
          align_up((size_t)n_omega * tc * sizeof(float));
 }
 
 size_t mfma_project_workspace(int precision, int N, int R, int n_occ, int n_unocc) {
-  if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_project_workspace(N, R, n_occ * n_unocc);
+  if (tiled_path(precision)) return tiled_project_workspace(N, R, n_occ, n_unocc);
   return split_u_bytes(precision, N, R);
 }
 
@@ -1067,6 +1072,10 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
   if (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2)
     return tiled_project(s, N, R, n_occ, n_unocc, static_cast<const float2*>(U), static_cast<const float2*>(psi_occ),
                          static_cast<const float2*>(psi_unocc), static_cast<float2*>(M), ws);
+  if (precision == GW_SPLIT_FP16 && g_fp16_core == 2)
+    return tiled_project_f16(s, N, R, n_occ, n_unocc, static_cast<const float2*>(U),
+                             static_cast<const float2*>(psi_occ), static_cast<const float2*>(psi_unocc),
+                             static_cast<float2*>(M), ws);
   const int word = word_of(precision);
   const int Rp = round_up(R, KS);
   Carver cv(ws);
@@ -1101,6 +1110,7 @@ int mfma_project(hipStream_t s, int precision, int N, int R, int n_occ, int n_un
 int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
                       const OmegaList& om, void* ws) {
   if (d.precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) return tiled_polarization(s, d, chunks, tc, om, ws);
+  if (d.precision == GW_SPLIT_FP16 && g_fp16_core == 2) return tiled_polarization_f16(s, d, chunks, tc, om, ws);
   Carver cv(ws);
   const int Rp = round_up(d.R, KS);
   uint32_t* Uh = nullptr;
@@ -1161,6 +1171,7 @@ extern "C" int gw_get_tuning(const char* key, int* value) {
   else if (k == "gemm_staging") *value = gw::g_gemm_staging;
   else if (k == "bf16_pipeline") *value = gw::g_bf16_pipeline;
   else if (k == "complex_product") *value = gw::g_complex_product;
+  else if (k == "fp16_core") *value = gw::g_fp16_core;
   else return gw::fail(GW_ERR_INVALID_ARG, std::string("gw_get_tuning: unknown key ") + key);
   return GW_OK;
 }
@@ -1176,6 +1187,11 @@ extern "C" int gw_set_tuning(const char* key, int value) {
   if (k == "gemm_staging") {
     if (value < 1 || value > 4) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: gemm_staging is 1 to 4");
     gw::g_gemm_staging = value;
+    return GW_OK;
+  }
+  if (k == "fp16_core") {
+    if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: fp16_core is 1 or 2");
+    gw::g_fp16_core = value;
     return GW_OK;
   }
   if (k == "complex_product") {

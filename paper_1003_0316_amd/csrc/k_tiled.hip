@@ -76,13 +76,48 @@ __device__ inline int lane_off(int sh, int row) { return (sh * TR + row) * 4; }
 constexpr int HWD = TR * 8;           // dwords per plane word per block-stage (1024 = 4 KB)
 __device__ inline int lane_off3(int h, int row) { return (h * TR + row) * 4; }
 
+// Plane words in BF16 (W = 0) or FP16 (W = 1).  FP16 words carry a power of
+// two scale per operand row (or pair) that puts the row's largest value in
+// [2^13, 2^14), so hi stays far below FP16's maximum and lo in its normal
+// range, and both splits accumulate into one FP32 set; the epilogues divide
+// the scales out.
+typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+__device__ inline uint32_t pack_f16(float a, float b) {
+  halfx2 v = {(_Float16)a, (_Float16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+template <int W>
+__device__ inline uint32_t pack_w(float a, float b) {
+  if constexpr (W == 0) return pack_bf16(a, b);
+  else return pack_f16(a, b);
+}
+
+template <int W>
+__device__ inline void split_w(float x, float& h, float& l) {
+  if constexpr (W == 0) h = (float)(__bf16)x;
+  else h = (float)(_Float16)x;
+  l = x - h;
+}
+
+// power of two s with mx * s in [2^13, 2^14) (1 if mx is 0 or not finite)
+__device__ inline float pow2_scale14(float mx) {
+  if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+  int e;
+  frexpf(mx, &e);
+  return ldexpf(1.f, 14 - e);
+}
+
 // 8 values -> hi and lo plane-word vectors.
+template <int W>
 __device__ inline void pack_plane(const float (&v)[8], uint4& hi, uint4& lo) {
   float h[8], l[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) split2(v[q], h[q], l[q]);
-  hi = make_uint4(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]), pack_bf16(h[4], h[5]), pack_bf16(h[6], h[7]));
-  lo = make_uint4(pack_bf16(l[0], l[1]), pack_bf16(l[2], l[3]), pack_bf16(l[4], l[5]), pack_bf16(l[6], l[7]));
+  for (int q = 0; q < 8; ++q) split_w<W>(v[q], h[q], l[q]);
+  hi = make_uint4(pack_w<W>(h[0], h[1]), pack_w<W>(h[2], h[3]), pack_w<W>(h[4], h[5]), pack_w<W>(h[6], h[7]));
+  lo = make_uint4(pack_w<W>(l[0], l[1]), pack_w<W>(l[2], l[3]), pack_w<W>(l[4], l[5]), pack_w<W>(l[6], l[7]));
 }
 
 // ------------------------------------------------------------ operand tiling
@@ -259,9 +294,10 @@ __global__ void scale_split_kernel(int nI, int nIe, int nstT, int Tp, int n_omeg
 
 // ---- operands of the three-multiplication form
 // U (c64 [N][R]) -> plane words [nI][nst][6][HWD]: re hi, lo, im hi, lo,
-// (re + im) hi, lo.  Rows >= N and k >= R are zero.
+// (re + im) hi, lo.  Rows >= N and k >= R are zero.  FP16: row I scaled by su[I].
+template <int W>
 __global__ void tile_u3_kernel(int N, int R, int nI, int nst, const float2* __restrict__ U,
-                               uint32_t* __restrict__ out) {
+                               const float* __restrict__ su, uint32_t* __restrict__ out) {
   const size_t total = (size_t)nI * nst * 2 * TR;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const int row = (int)(e % TR);
@@ -270,24 +306,25 @@ __global__ void tile_u3_kernel(int N, int R, int nI, int nst, const float2* __re
     const int st = (int)(bs % nst), blk = (int)(bs / nst);
     const int I = blk * TR + row;
     const int r0 = st * TK + 8 * h;
+    const float sc = (W == 1 && I < N) ? su[I] : 1.f;
     float re[8], im[8], sm[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       float2 x = make_float2(0.f, 0.f);
       if (I < N && r0 + q < R) x = U[(size_t)I * R + r0 + q];
-      re[q] = x.x;
-      im[q] = x.y;
-      sm[q] = x.x + x.y;
+      re[q] = x.x * sc;
+      im[q] = x.y * sc;
+      sm[q] = (x.x + x.y) * sc;
     }
     uint32_t* o = out + bs * 6 * HWD + lane_off3(h, row);
     uint4 hi, lo;
-    pack_plane(re, hi, lo);
+    pack_plane<W>(re, hi, lo);
     *reinterpret_cast<uint4*>(o) = hi;
     *reinterpret_cast<uint4*>(o + HWD) = lo;
-    pack_plane(im, hi, lo);
+    pack_plane<W>(im, hi, lo);
     *reinterpret_cast<uint4*>(o + 2 * HWD) = hi;
     *reinterpret_cast<uint4*>(o + 3 * HWD) = lo;
-    pack_plane(sm, hi, lo);
+    pack_plane<W>(sm, hi, lo);
     *reinterpret_cast<uint4*>(o + 4 * HWD) = hi;
     *reinterpret_cast<uint4*>(o + 5 * HWD) = lo;
   }
@@ -297,8 +334,14 @@ __global__ void tile_u3_kernel(int N, int R, int nI, int nst, const float2* __re
 // [nT][nst][6][HWD] (re, im, re + im; hi, lo), pairs t >= T and k >= R zero.
 // Same two phases as pair_product_kernel: rows read as 256-byte segments into
 // an LDS tile, then lane = pair, 8 k per item, 1 KB per store.
+// FP16: pair t scaled by a power of two from the band maxima bmo (rows of po)
+// and bmu (rows of pu), |F_t| <= bmo bmu and its planes <= sqrt(2) bmo bmu;
+// the scales go to sF[t] (1 past T), written by the first stage-block.
+template <int W>
 __global__ __launch_bounds__(256) void pair_product3_kernel(int R, int nst, int nT, const float2* __restrict__ po,
                                                             const float2* __restrict__ pu, int nu, long tb, int T,
+                                                            const float* __restrict__ bmo,
+                                                            const float* __restrict__ bmu, float* __restrict__ sF,
                                                             uint32_t* __restrict__ out) {
   __shared__ float2 F[TR * PP_PITCH];
   const int blk = blockIdx.y;
@@ -337,25 +380,34 @@ __global__ __launch_bounds__(256) void pair_product3_kernel(int R, int nst, int 
   for (int it = 0; it < (TR * PP_K / 8) / 256; ++it) {
     const int item = it * 256 + tid;
     const int p = item & (TR - 1), grp = item >> 7;   // grp: 0..3 (stage = grp / 2, h = grp % 2)
+    float sc = 1.f;
+    if constexpr (W == 1) {
+      const int t = blk * TR + p;
+      if (t < T) {
+        const long g = tb + t;
+        sc = pow2_scale14(1.41421356f * bmo[g / nu] * bmu[g % nu]);
+      }
+      if (blockIdx.x == 0 && grp == 0) sF[t] = sc;
+    }
     float re[8], im[8], sm[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const float2 f = F[p * PP_PITCH + grp * 8 + q];
-      re[q] = f.x;
-      im[q] = f.y;
-      sm[q] = f.x + f.y;
+      re[q] = f.x * sc;
+      im[q] = f.y * sc;
+      sm[q] = (f.x + f.y) * sc;
     }
     const int st = st0 + (grp >> 1);
     if (st < nst) {
       uint32_t* o = out + ((size_t)blk * nst + st) * 6 * HWD + lane_off3(grp & 1, p);
       uint4 hi, lo;
-      pack_plane(re, hi, lo);
+      pack_plane<W>(re, hi, lo);
       *reinterpret_cast<uint4*>(o) = hi;
       *reinterpret_cast<uint4*>(o + HWD) = lo;
-      pack_plane(im, hi, lo);
+      pack_plane<W>(im, hi, lo);
       *reinterpret_cast<uint4*>(o + 2 * HWD) = hi;
       *reinterpret_cast<uint4*>(o + 3 * HWD) = lo;
-      pack_plane(sm, hi, lo);
+      pack_plane<W>(sm, hi, lo);
       *reinterpret_cast<uint4*>(o + 4 * HWD) = hi;
       *reinterpret_cast<uint4*>(o + 5 * HWD) = lo;
     }
@@ -366,8 +418,11 @@ __global__ __launch_bounds__(256) void pair_product3_kernel(int R, int nst, int 
 // words [n_omega][nIe][nstT][8][HWD]: a = re x, b = im x, a + b, a - b (hi,
 // lo each); the accumulation reads planes 0..5 as its first operand and
 // planes 0..3, 6, 7 as the second.  Blocks in [nI, nIe) are zero.
+// FP16: row I of frequency j scaled by sX[j * nIe * TR + I].
+template <int W>
 __global__ void scale_split3_kernel(int nI, int nIe, int nstT, int Tp, int n_omega, const float2* __restrict__ Mt,
-                                    const float* __restrict__ sw, uint32_t* __restrict__ X) {
+                                    const float* __restrict__ sw, const float* __restrict__ sX,
+                                    uint32_t* __restrict__ X) {
   const size_t total = (size_t)nIe * nstT * 2 * TR;
   const size_t xstride = (size_t)nIe * nstT * 8 * HWD;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
@@ -395,7 +450,8 @@ __global__ void scale_split3_kernel(int nI, int nIe, int nstT, int Tp, int n_ome
     for (int jw = 0; jw < n_omega; ++jw) {
       const float4 s0 = *reinterpret_cast<const float4*>(sw + (size_t)jw * Tp + t0);
       const float4 s1 = *reinterpret_cast<const float4*>(sw + (size_t)jw * Tp + t0 + 4);
-      const float sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+      const float rs = W == 1 ? sX[(size_t)jw * nIe * TR + blk * TR + row] : 1.f;
+      const float sv[8] = {s0.x * rs, s0.y * rs, s0.z * rs, s0.w * rs, s1.x * rs, s1.y * rs, s1.z * rs, s1.w * rs};
       float a[8], b[8], ps[8], ms[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -406,20 +462,97 @@ __global__ void scale_split3_kernel(int nI, int nIe, int nstT, int Tp, int n_ome
       }
       uint32_t* oj = o + (size_t)jw * xstride;
       uint4 hi, lo;
-      pack_plane(a, hi, lo);
+      pack_plane<W>(a, hi, lo);
       *reinterpret_cast<uint4*>(oj) = hi;
       *reinterpret_cast<uint4*>(oj + HWD) = lo;
-      pack_plane(b, hi, lo);
+      pack_plane<W>(b, hi, lo);
       *reinterpret_cast<uint4*>(oj + 2 * HWD) = hi;
       *reinterpret_cast<uint4*>(oj + 3 * HWD) = lo;
-      pack_plane(ps, hi, lo);
+      pack_plane<W>(ps, hi, lo);
       *reinterpret_cast<uint4*>(oj + 4 * HWD) = hi;
       *reinterpret_cast<uint4*>(oj + 5 * HWD) = lo;
-      pack_plane(ms, hi, lo);
+      pack_plane<W>(ms, hi, lo);
       *reinterpret_cast<uint4*>(oj + 6 * HWD) = hi;
       *reinterpret_cast<uint4*>(oj + 7 * HWD) = lo;
     }
   }
+}
+
+// ---- scales of the FP16 plane words
+// su[I] for row I of U: the largest of |re|, |im|, |re + im| over the grid.
+__global__ __launch_bounds__(256) void rowscale_u_kernel(int R, const float2* __restrict__ U, float* __restrict__ su) {
+  __shared__ float red[256];
+  const float2* u = U + (size_t)blockIdx.x * R;
+  float m = 0.f;
+  for (int r = threadIdx.x; r < R; r += 256) {
+    const float2 x = u[r];
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fabsf(x.x + x.y)));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) su[blockIdx.x] = pow2_scale14(red[0]);
+}
+
+// bm[row] = max over the grid of |psi_row(r)| (one block per band row).
+__global__ __launch_bounds__(256) void bandmax_kernel(int R, const float2* __restrict__ psi, float* __restrict__ bm) {
+  __shared__ float red[256];
+  const float2* p = psi + (size_t)blockIdx.x * R;
+  float m = 0.f;
+  for (int r = threadIdx.x; r < R; r += 256) {
+    const float2 x = p[r];
+    m = fmaxf(m, x.x * x.x + x.y * x.y);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bm[blockIdx.x] = sqrtf(red[0]);
+}
+
+// mrow[I] = max over the chunk's pairs of |M_It| (tiled M, one block per row
+// block: lane = row, two halves of the stages combined in LDS); rows of the
+// padding blocks [nI, nIe) get 0.
+__global__ __launch_bounds__(256) void mrow_kernel(int nI, int nstT, const float2* __restrict__ Mt,
+                                                   float* __restrict__ mrow) {
+  __shared__ float red[256];
+  const int blk = blockIdx.x, row = threadIdx.x & (TR - 1), half = threadIdx.x >> 7;
+  float m = 0.f;
+  if (blk < nI)
+    for (int st = half; st < nstT; st += 2)
+#pragma unroll
+      for (int sh = 0; sh < 4; ++sh) {
+        const float4* src = reinterpret_cast<const float4*>(Mt + ((((size_t)blk * nstT + st) * 4 + sh) * TR + row) * 4);
+        const float4 a = src[0], b = src[1];
+        m = fmaxf(m, fmaxf(fmaxf(a.x * a.x + a.y * a.y, a.z * a.z + a.w * a.w),
+                           fmaxf(b.x * b.x + b.y * b.y, b.z * b.z + b.w * b.w)));
+      }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  if (half == 0) mrow[blk * TR + row] = sqrtf(fmaxf(red[row], red[row + TR]));
+}
+
+// sX[j][I] for the scaled operands X_j = s_j M: the bound sqrt(2) max_t |M_It|
+// max_t s_j(t) of their planes (a, b, a + b, a - b).
+__global__ __launch_bounds__(256) void xscale_kernel(int rows, int Tp, const float* __restrict__ sw,
+                                                     const float* __restrict__ mrow, float* __restrict__ sX) {
+  __shared__ float red[256];
+  const int j = blockIdx.x;
+  float m = 0.f;
+  for (int t = threadIdx.x; t < Tp; t += 256) m = fmaxf(m, sw[(size_t)j * Tp + t]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const float smax = red[0];
+  for (int I = threadIdx.x; I < rows; I += 256) sX[(size_t)j * rows + I] = pow2_scale14(1.41421356f * mrow[I] * smax);
 }
 
 // W^c_j = W_j - diag(v) (c128 [N][N]) -> A-side words [nI][nstN][4][WD]
@@ -684,6 +817,11 @@ struct GemmArgs {
   // the sign s of Re = T1 + s T2, Im = T3 - T1 + s T2
   int a_words3, b_words3, b_sum3;
   float sigma3;
+  // FP16 plane words: scales of the A rows and B columns (projection), or of
+  // the rows of frequency jw at sa + jw * s_stride (accumulation, both sides)
+  const float* sa;
+  const float* sb;
+  size_t s_stride;
 };
 
 __device__ inline floatx16 mma(uint4 a, uint4 b, floatx16 c) {
@@ -1388,7 +1526,17 @@ __device__ __forceinline__ void stage_dma3(uint32_t* L, const GemmArgs& g, const
   }
 }
 
-template <int OUT>
+template <int W>
+__device__ inline floatx16 mma3(uint4 a, uint4 b, floatx16 c) {
+  if constexpr (W == 0)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a), __builtin_bit_cast(halfx8, b), c, 0,
+                                                  0, 0);
+}
+
+template <int OUT, int W>
 __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   int ti, tj, jw;
@@ -1437,9 +1585,9 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
-          t[p][rb][cb] = mma(ah[rb], bh[cb], t[p][rb][cb]);
-          t[p][rb][cb] = mma(ah[rb], bl[cb], t[p][rb][cb]);
-          t[p][rb][cb] = mma(al[rb], bh[cb], t[p][rb][cb]);
+          t[p][rb][cb] = mma3<W>(ah[rb], bh[cb], t[p][rb][cb]);
+          t[p][rb][cb] = mma3<W>(ah[rb], bl[cb], t[p][rb][cb]);
+          t[p][rb][cb] = mma3<W>(al[rb], bh[cb], t[p][rb][cb]);
         }
     }
   }
@@ -1459,7 +1607,12 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
             for (int v = 0; v < 16; ++v) {
               const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
               const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
-              E[row * 128 + c0 + cb * 32 + l32] = make_float2(t1 + sg * t2, t3 - t1 + sg * t2);
+              float un = 1.f;
+              if constexpr (W == 1) {
+                const float* sj = g.sa + (size_t)jw * g.s_stride;
+                un = 1.f / (sj[ti * TM + row] * sj[tj * TN + c * 128 + c0 + cb * 32 + l32]);
+              }
+              E[row * 128 + c0 + cb * 32 + l32] = make_float2((t1 + sg * t2) * un, (t3 - t1 + sg * t2) * un);
             }
       }
       __syncthreads();
@@ -1489,7 +1642,9 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
         const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         const int col = wn * 64 + cb * 32 + l32;
         const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
-        const float re = t1 + sg * t2, im = t3 - t1 + sg * t2;
+        float un = 1.f;
+        if constexpr (W == 1) un = 1.f / (g.sa[ti * TM + row] * g.sb[tj * TN + col]);
+        const float re = (t1 + sg * t2) * un, im = (t3 - t1 + sg * t2) * un;
         if constexpr (OUT == OUT_TILED) {
           const int tt = tj * TN + col;
           const size_t bs = (size_t)ti * g.nst_out + tt / TK;
@@ -1541,6 +1696,7 @@ struct TiledDims {
   int nI, nIe, nstR, Tp, nT, nstT;
   size_t u_words, q_words, m_c64, x_words, sw_f32;
   size_t u3_words, q3_words, x3_words;   // the three-multiplication core's plane words
+  size_t n_scale;                         // FP16 scales: U rows, pairs, M row maxima, X rows
   TiledDims(int N, int R, int T, int n_omega) {
     nI = cdiv(N, TR);
     nIe = (nI + 1) & ~1;
@@ -1556,6 +1712,7 @@ struct TiledDims {
     u3_words = (size_t)nI * nstR * 6 * HWD;
     q3_words = (size_t)nT * nstR * 6 * HWD;
     x3_words = (size_t)n_omega * nIe * nstT * 8 * HWD;
+    n_scale = (size_t)nIe * TR * 2 + Tp + (size_t)n_omega * nIe * TR;
     // one workspace layout serves both cores (the larger of each array)
     u_words = std::max(u_words, u3_words);
     q_words = std::max(q_words, q3_words);
@@ -1563,7 +1720,7 @@ struct TiledDims {
   }
   size_t bytes() const {
     return align_up(u_words * 4) + align_up(q_words * 4) + align_up(m_c64 * 8) + align_up(x_words * 4) +
-           align_up(sw_f32 * 4);
+           align_up(sw_f32 * 4) + align_up(n_scale * 4) + 8 * 256;   // + alignment of the scale arrays
   }
 };
 
@@ -1608,16 +1765,16 @@ int launch_gemm8(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
   return GW_OK;
 }
 
-template <int OUT>
+template <int OUT, int W>
 int launch_gemm3m(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
   static int attr = 0;
   if (!attr) {
-    GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm3m_kernel<OUT>),
+    GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm3m_kernel<OUT, W>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemm3Lds));
     attr = 1;
   }
   ProfScope prof(s, name);
-  hipLaunchKernelGGL((gemm3m_kernel<OUT>), dim3(grid), dim3(GT8), kGemm3Lds, s, a);
+  hipLaunchKernelGGL((gemm3m_kernel<OUT, W>), dim3(grid), dim3(GT8), kGemm3Lds, s, a);
   GW_LAUNCHED("gemm3m_kernel");
   return GW_OK;
 }
@@ -1629,19 +1786,43 @@ int launch_gemm(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
   return g_gemm_staging == 2 ? launch_gemm_as<OUT, 1>(s, a, grid, name) : launch_gemm_as<OUT, 0>(s, a, grid, name);
 }
 
-int launch_tile_u3(hipStream_t s, const TiledDims& d, int N, int R, const float2* U, uint32_t* Uw) {
-  hipLaunchKernelGGL(tile_u3_kernel, dim3(stream_blocks((size_t)d.nI * d.nstR * 2 * TR)), dim3(256), 0, s, N, R,
-                     d.nI, d.nstR, U, Uw);
+__global__ void fill_f32_kernel(float* __restrict__ p, int n, float v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// FP16 row scales of U (rows past N: 1), then the plane words.
+template <int W>
+int launch_tile_u3(hipStream_t s, const TiledDims& d, int N, int R, const float2* U, float* su, uint32_t* Uw) {
+  if constexpr (W == 1) {
+    hipLaunchKernelGGL(rowscale_u_kernel, dim3(N), dim3(256), 0, s, R, U, su);
+    GW_LAUNCHED("rowscale_u_kernel");
+    const int pad = d.nIe * TR - N;
+    if (pad > 0) {
+      hipLaunchKernelGGL(fill_f32_kernel, dim3(cdiv(pad, 256)), dim3(256), 0, s, su + N, pad, 1.f);
+      GW_LAUNCHED("fill_f32_kernel");
+    }
+  }
+  hipLaunchKernelGGL(tile_u3_kernel<W>, dim3(stream_blocks((size_t)d.nI * d.nstR * 2 * TR)), dim3(256), 0, s, N, R,
+                     d.nI, d.nstR, U, su, Uw);
   GW_LAUNCHED("tile_u3_kernel");
   return GW_OK;
 }
 
+template <int W>
 int launch_pair_product3(hipStream_t s, const TiledDims& d, int R, const float2* po, const float2* pu, int nu, long tb,
-                         int T, uint32_t* Q) {
+                         int T, const float* bmo, const float* bmu, float* sF, uint32_t* Q) {
   ProfScope prof(s, "pair_product_kernel");
-  hipLaunchKernelGGL(pair_product3_kernel, dim3((d.nstR + 1) / 2, d.nT), dim3(256), 0, s, R, d.nstR, d.nT, po, pu,
-                     nu, tb, T, Q);
+  hipLaunchKernelGGL(pair_product3_kernel<W>, dim3((d.nstR + 1) / 2, d.nT), dim3(256), 0, s, R, d.nstR, d.nT, po,
+                     pu, nu, tb, T, bmo, bmu, sF, Q);
   GW_LAUNCHED("pair_product3_kernel");
+  return GW_OK;
+}
+
+int launch_bandmax(hipStream_t s, int rows, int R, const float2* psi, float* bm) {
+  if (rows < 1) return GW_OK;
+  hipLaunchKernelGGL(bandmax_kernel, dim3(rows), dim3(256), 0, s, R, psi, bm);
+  GW_LAUNCHED("bandmax_kernel");
   return GW_OK;
 }
 
@@ -1663,22 +1844,147 @@ void set_projection3(GemmArgs& a, const TiledDims& d, const uint32_t* Uw, const 
   a.T = T;
 }
 
+// The three-multiplication pipeline.  Carver cv continues after the main
+// arrays: the FP16 scales and band maxima are taken from it.
+template <int W>
+int tiled_project3(hipStream_t s, const TiledDims& d, int N, int R, int n_occ, int n_unocc, const float2* U,
+                   const float2* po, const float2* pu, float2* M, uint32_t* Uw, uint32_t* Q, Carver& cv) {
+  const int T = n_occ * n_unocc;
+  float* su = cv.take<float>((size_t)d.nIe * TR);
+  float* sF = cv.take<float>(d.Tp);
+  float* bmo = cv.take<float>(n_occ);
+  float* bmu = cv.take<float>(n_unocc);
+  int st;
+  if (W == 1) {
+    if ((st = launch_bandmax(s, n_occ, R, po, bmo)) != GW_OK) return st;
+    if ((st = launch_bandmax(s, n_unocc, R, pu, bmu)) != GW_OK) return st;
+  }
+  if ((st = launch_tile_u3<W>(s, d, N, R, U, su, Uw)) != GW_OK) return st;
+  if ((st = launch_pair_product3<W>(s, d, R, po, pu, n_unocc, 0, T, bmo, bmu, sF, Q)) != GW_OK) return st;
+  GemmArgs a{};
+  set_projection3(a, d, Uw, Q, N, T);
+  a.M = M;
+  a.ldm = T;
+  a.sa = su;
+  a.sb = sF;
+  return launch_gemm3m<OUT_ROWS, W>(s, a, d.nI * a.nTj, W ? "project_rows_f16_kernel" : "project_rows_bf16_kernel");
+}
+
+template <int W>
+int tiled_polarization3(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, const TiledDims& dm,
+                        const OmegaList& om, uint32_t* Uw, uint32_t* Q, float2* Mt, uint32_t* X, float* sw,
+                        Carver& cv) {
+  const float2* psi = static_cast<const float2*>(d.psi);
+  const int nb = d.n_occ + d.n_unocc;
+  const int n_tiles = count_lower_tiles(dm.nI);
+  const int srows = dm.nIe * TR;
+  float* su = cv.take<float>(srows);
+  float* sF = cv.take<float>(dm.Tp);
+  float* mrow = cv.take<float>(srows);
+  float* sX = cv.take<float>((size_t)d.n_omega * srows);
+  float* bm = cv.take<float>((size_t)d.n_k * nb);
+  int st;
+  if (W == 1 && (st = launch_bandmax(s, d.n_k * nb, d.R, psi, bm)) != GW_OK) return st;
+  if ((st = launch_tile_u3<W>(s, dm, d.N, d.R, static_cast<const float2*>(d.U), su, Uw)) != GW_OK) return st;
+  for (const Chunk& c : chunks) {
+    // the chunk arrays are sized for the longest chunk; a shorter one pads with zeros
+    TiledDims cd(d.N, d.R, c.T, d.n_omega);
+    const float2* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
+    const float2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
+    const float* bmo = bm + (size_t)c.k * nb + c.n0;
+    const float* bmu = bm + (size_t)c.kq * nb + d.n_occ + c.u0;
+    hipLaunchKernelGGL(weights_sqrt_kernel, dim3(cdiv(cd.Tp, 256)), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om,
+                       cd.Tp, sw);
+    GW_LAUNCHED("weights_sqrt_kernel");
+    if ((st = launch_pair_product3<W>(s, cd, d.R, po, pu, c.nu, c.tb, c.T, bmo, bmu, sF, Q)) != GW_OK) return st;
+    GemmArgs a{};
+    set_projection3(a, cd, Uw, Q, d.N, c.T);
+    a.M = Mt;
+    a.nst_out = cd.nstT;
+    a.sa = su;
+    a.sb = sF;
+    if ((st = launch_gemm3m<OUT_TILED, W>(s, a, cd.nI * a.nTj, W ? "project_f16_kernel" : "project_bf16_kernel")) !=
+        GW_OK)
+      return st;
+    if (W == 1) {
+      hipLaunchKernelGGL(mrow_kernel, dim3(cd.nIe), dim3(256), 0, s, cd.nI, cd.nstT, Mt, mrow);
+      GW_LAUNCHED("mrow_kernel");
+      hipLaunchKernelGGL(xscale_kernel, dim3(d.n_omega), dim3(256), 0, s, srows, cd.Tp, sw, mrow, sX);
+      GW_LAUNCHED("xscale_kernel");
+    }
+    {
+      ProfScope prof(s, "scale_split_kernel");
+      hipLaunchKernelGGL(scale_split3_kernel<W>, dim3(stream_blocks((size_t)cd.nIe * cd.nstT * 2 * TR)), dim3(256), 0,
+                         s, cd.nI, cd.nIe, cd.nstT, cd.Tp, d.n_omega, Mt, sw, sX, X);
+      GW_LAUNCHED("scale_split3_kernel");
+    }
+    GemmArgs b{};
+    b.A = X;
+    b.B = X;
+    b.a_words3 = 8;
+    b.b_words3 = 8;
+    b.b_sum3 = 6;
+    b.sigma3 = 1.f;
+    b.nst = cd.nstT;
+    b.a_bstride = (size_t)cd.nstT * 8 * HWD;
+    b.b_bstride = (size_t)cd.nstT * 8 * HWD;
+    b.omega_stride = (size_t)cd.nIe * cd.nstT * 8 * HWD;
+    b.nI = cd.nI;
+    b.n_tiles = n_tiles;
+    b.N = d.N;
+    b.P = reinterpret_cast<double2*>(d.P);
+    b.sa = sX;
+    b.sb = sX;
+    b.s_stride = srows;
+    if ((st = launch_gemm3m<OUT_HERK, W>(s, b, n_tiles * d.n_omega, W ? "herk_f16_kernel" : "herk_bf16_kernel")) !=
+        GW_OK)
+      return st;
+  }
+  return GW_OK;
+}
+
 }  // namespace
 
-size_t tiled_pol_workspace(int N, int R, int tc, int n_omega) { return TiledDims(N, R, tc, n_omega).bytes(); }
+size_t tiled_pol_workspace(int N, int R, int tc, int n_omega, size_t psi_rows) {
+  return TiledDims(N, R, tc, n_omega).bytes() + align_up(psi_rows * 4);
+}
 
-size_t tiled_project_workspace(int N, int R, int T) { return TiledDims(N, R, T, 0).bytes(); }
+size_t tiled_project_workspace(int N, int R, int n_occ, int n_unocc) {
+  return TiledDims(N, R, n_occ * n_unocc, 0).bytes() + 2 * align_up((size_t)std::max(n_occ, n_unocc) * 4);
+}
+
+int tiled_polarization_f16(hipStream_t s, const gw_pol_desc& d, const std::vector<Chunk>& chunks, int tc,
+                           const OmegaList& om, void* ws) {
+  TiledDims dm(d.N, d.R, tc, d.n_omega);
+  Carver cv(ws);
+  uint32_t* Uw = cv.take<uint32_t>(dm.u_words);
+  uint32_t* Q = cv.take<uint32_t>(dm.q_words);
+  float2* Mt = cv.take<float2>(dm.m_c64);
+  uint32_t* X = cv.take<uint32_t>(dm.x_words);
+  float* sw = cv.take<float>(dm.sw_f32);
+  return tiled_polarization3<1>(s, d, chunks, dm, om, Uw, Q, Mt, X, sw, cv);
+}
+
+int tiled_project_f16(hipStream_t s, int N, int R, int n_occ, int n_unocc, const float2* U, const float2* po,
+                      const float2* pu, float2* M, void* ws) {
+  TiledDims d(N, R, n_occ * n_unocc, 0);
+  Carver cv(ws);
+  uint32_t* Uw = cv.take<uint32_t>(d.u_words);
+  uint32_t* Q = cv.take<uint32_t>(d.q_words);
+  return tiled_project3<1>(s, d, N, R, n_occ, n_unocc, U, po, pu, M, Uw, Q, cv);
+}
 
 int tiled_default_chunk_pairs(int N, int R, int n_omega) {
   // Whole 256-pair tiles.  The projection grid (row blocks x pair tiles)
   // should fill complete rounds of the 256 compute units; the accumulation
-  // adds each chunk into the FP64 P once, so longer chunks amortise that
-  // read-modify-write; the chunk's arrays (products, scaled copies per
-  // frequency) stay within 16 GB.
+  // adds each chunk into the FP64 P once per frequency, so longer chunks
+  // amortise that read-modify-write (at N = 6000 and 16 frequencies it is
+  // 9.2 GB per chunk); the chunk's arrays (product planes, 12 bytes per
+  // complex value, and the scaled copies per frequency) stay within 32 GB.
   const long rows = cdiv(N, TR);
   const long nIe = (rows + 1) & ~1L;
-  const size_t per_tile = (size_t)TN * ((size_t)cdiv(R, TK) * TK * 8 + (size_t)n_omega * nIe * TR * 16);
-  const long cap = std::max<long>(1, std::min<long>(32, (long)(((size_t)16 << 30) / per_tile)));
+  const size_t per_tile = (size_t)TN * ((size_t)cdiv(R, TK) * TK * 12 + (size_t)n_omega * nIe * TR * 16);
+  const long cap = std::max<long>(1, std::min<long>(64, (long)(((size_t)32 << 30) / per_tile)));
   long best_x = 1;
   double best = -1.0;
   for (long x = 1; x <= cap; ++x) {
@@ -1700,15 +2006,7 @@ int tiled_project(hipStream_t s, int N, int R, int n_occ, int n_unocc, const flo
   uint32_t* Uw = cv.take<uint32_t>(d.u_words);
   uint32_t* Q = cv.take<uint32_t>(d.q_words);
   int st;
-  if (g_complex_product == 3) {
-    if ((st = launch_tile_u3(s, d, N, R, U, Uw)) != GW_OK) return st;
-    if ((st = launch_pair_product3(s, d, R, po, pu, n_unocc, 0, T, Q)) != GW_OK) return st;
-    GemmArgs a{};
-    set_projection3(a, d, Uw, Q, N, T);
-    a.M = M;
-    a.ldm = T;
-    return launch_gemm3m<OUT_ROWS>(s, a, d.nI * a.nTj, "project_rows_bf16_kernel");
-  }
+  if (g_complex_product == 3) return tiled_project3<0>(s, d, N, R, n_occ, n_unocc, U, po, pu, M, Uw, Q, cv);
   if ((st = launch_tile_u(s, d, N, R, U, Uw)) != GW_OK) return st;
   if ((st = launch_pair_product(s, d, R, po, pu, n_unocc, 0, T, Q)) != GW_OK) return st;
   GemmArgs a{};
@@ -1740,46 +2038,7 @@ int tiled_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Ch
   const int nb = d.n_occ + d.n_unocc;
   int st;
   const int n_tiles = count_lower_tiles(dm.nI);
-  if (g_complex_product == 3) {
-    if ((st = launch_tile_u3(s, dm, d.N, d.R, static_cast<const float2*>(d.U), Uw)) != GW_OK) return st;
-    for (const Chunk& c : chunks) {
-      TiledDims cd(d.N, d.R, c.T, d.n_omega);
-      const float2* po = psi + ((size_t)c.k * nb + c.n0) * d.R;
-      const float2* pu = psi + ((size_t)c.kq * nb + d.n_occ + c.u0) * d.R;
-      hipLaunchKernelGGL(weights_sqrt_kernel, dim3(cdiv(cd.Tp, 256)), dim3(256), 0, s, d.eps, nb, d.n_occ, c, om,
-                         cd.Tp, sw);
-      GW_LAUNCHED("weights_sqrt_kernel");
-      if ((st = launch_pair_product3(s, cd, d.R, po, pu, c.nu, c.tb, c.T, Q)) != GW_OK) return st;
-      GemmArgs a{};
-      set_projection3(a, cd, Uw, Q, d.N, c.T);
-      a.M = Mt;
-      a.nst_out = cd.nstT;
-      if ((st = launch_gemm3m<OUT_TILED>(s, a, cd.nI * a.nTj, "project_bf16_kernel")) != GW_OK) return st;
-      {
-        ProfScope prof(s, "scale_split_kernel");
-        hipLaunchKernelGGL(scale_split3_kernel, dim3(stream_blocks((size_t)cd.nIe * cd.nstT * 2 * TR)), dim3(256), 0,
-                           s, cd.nI, cd.nIe, cd.nstT, cd.Tp, d.n_omega, Mt, sw, X);
-        GW_LAUNCHED("scale_split3_kernel");
-      }
-      GemmArgs b{};
-      b.A = X;
-      b.B = X;
-      b.a_words3 = 8;
-      b.b_words3 = 8;
-      b.b_sum3 = 6;
-      b.sigma3 = 1.f;
-      b.nst = cd.nstT;
-      b.a_bstride = (size_t)cd.nstT * 8 * HWD;
-      b.b_bstride = (size_t)cd.nstT * 8 * HWD;
-      b.omega_stride = (size_t)cd.nIe * cd.nstT * 8 * HWD;
-      b.nI = cd.nI;
-      b.n_tiles = n_tiles;
-      b.N = d.N;
-      b.P = reinterpret_cast<double2*>(d.P);
-      if ((st = launch_gemm3m<OUT_HERK>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")) != GW_OK) return st;
-    }
-    return GW_OK;
-  }
+  if (g_complex_product == 3) return tiled_polarization3<0>(s, d, chunks, dm, om, Uw, Q, Mt, X, sw, cv);
   if ((st = launch_tile_u(s, dm, d.N, d.R, static_cast<const float2*>(d.U), Uw)) != GW_OK) return st;
   for (const Chunk& c : chunks) {
     // the chunk arrays are sized for tc pairs; a shorter last chunk pads with zeros

@@ -150,7 +150,8 @@ def test_tuning_switches_validate(b):
     """gw_set_tuning accepts the documented keys and values only (host-side)."""
     L = b.lib()
     for key, lo, hi, default in (("bf16_pipeline", 1, 2, 2), ("projection_variant", 1, 2, 2),
-                                 ("gemm_staging", 1, 4, 3), ("complex_product", 3, 4, 3)):
+                                 ("gemm_staging", 1, 4, 3), ("complex_product", 3, 4, 3),
+                                 ("fp16_core", 1, 2, 1)):
         assert b.gw_get_tuning(key) == default
         for v in (lo, hi):
             assert L.gw_set_tuning(key.encode(), v) == 0

@@ -250,3 +250,31 @@ def test_three_product_core(lib, shape):
     assert merr < 2e-5
     for j in range(Pg.shape[0]):
         assert np.array_equal(Pg[j], Pg[j].conj().T)
+
+
+@pytest.mark.parametrize("core", [1, 2])
+def test_split_fp16_cores(lib, core):
+    """Split FP16 on both kernel families: the operands staged inside the GEMM
+    kernels with main and correction accumulators (fp16_core 1, the default:
+    FP32-level accuracy), and the three-multiplication core on power-of-two
+    scaled plane words with one accumulator set (fp16_core 2: twice as fast,
+    accuracy of the split-BF16 class); ragged multi-tile shape, projection and
+    polarization."""
+    import torch
+    shape = dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150)
+    inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=13, omega=gwsynth.omega_mesh("m16"))
+    U, psi = _dev(inp)
+    try:
+        lib.gw_set_tuning("fp16_core", core)
+        P = lib.gw_polarization(U, psi, inp.eps, inp.omega, 3, precision="split_fp16", kq=inp.kq)
+        M = lib.gw_project(U, psi[0, :3].contiguous(), psi[0, 3:].contiguous(), "split_fp16")
+        torch.cuda.synchronize()
+    finally:
+        lib.gw_set_tuning("fp16_core", 1)
+    Ur, pr = _rounded(inp)
+    ref = orc.polarization(Ur, pr, inp.eps, inp.omega, 3, kq=inp.kq)
+    err = orc.rel_fro(P.cpu().numpy(), ref)
+    Mref = orc.projections(Ur, pr[0, :3], pr[0, 3:])
+    merr = np.linalg.norm(M.cpu().numpy() - Mref) / np.linalg.norm(Mref)
+    print(f"split FP16, core {core}: P max rel err {err.max():.2e}, M rel err {merr:.2e}")
+    assert err.max() < (1e-6 if core == 1 else 1e-5) and merr < 2e-6
