@@ -1502,8 +1502,15 @@ __global__ __launch_bounds__(GT8, 1) void gemm8pp_bf16x3_kernel(GemmArgs g) {
 // (144 KB).  Per stage and wave: for each plane, 4 A and 4 B fragments and 12
 // MFMAs (hi hi, hi lo, lo hi) -- 36 MFMAs and 24 LDS reads for 16 complex k,
 // against 48 MFMAs and 24 reads in the four-product core.
-constexpr int ST3 = 18 * HWD;                                    // dwords per LDS stage
-constexpr size_t kGemm3Lds = 2 * (size_t)ST3 * sizeof(uint32_t); // 144 KB
+//
+// The two stage buffers are two distinct LDS arrays and the stage loop is
+// unrolled by two, so that every buffer address is known at compile time.
+// The compiler then sees that the fragment reads of one buffer do not alias
+// the copy landing in the other, and lets the reads start while that copy is
+// in flight; with one array indexed by the stage parity it has to wait for
+// the copy (vmcnt 0) before the first read of every stage, which exposes the
+// full load latency once per stage.
+constexpr int ST3 = 18 * HWD;  // dwords per LDS stage (72 KB)
 
 // DMA of stage st into LDS buffer L: 72 chunks of 1 KB (A plane words 0..5,
 // then the two B halves' plane words), chunk q by wave q % 8.
@@ -1536,9 +1543,37 @@ __device__ inline floatx16 mma3(uint4 a, uint4 b, floatx16 c) {
                                                   0, 0);
 }
 
+// The 36 MFMAs of one stage from LDS buffer L.
+template <int W>
+__device__ __forceinline__ void stage_mma3(const uint32_t* L, int aoff, int boff, floatx16 (&t)[3][2][2]) {
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    uint4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      ah[rb] = *reinterpret_cast<const uint4*>(L + (2 * p) * HWD + aoff + rb * 128);
+      al[rb] = *reinterpret_cast<const uint4*>(L + (2 * p + 1) * HWD + aoff + rb * 128);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      bh[cb] = *reinterpret_cast<const uint4*>(L + boff + (2 * p) * HWD + cb * 128);
+      bl[cb] = *reinterpret_cast<const uint4*>(L + boff + (2 * p + 1) * HWD + cb * 128);
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        t[p][rb][cb] = mma3<W>(ah[rb], bh[cb], t[p][rb][cb]);
+        t[p][rb][cb] = mma3<W>(ah[rb], bl[cb], t[p][rb][cb]);
+        t[p][rb][cb] = mma3<W>(al[rb], bh[cb], t[p][rb][cb]);
+      }
+  }
+}
+
 template <int OUT, int W>
 __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
-  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  __shared__ __attribute__((aligned(16))) uint32_t lds0[ST3];
+  __shared__ __attribute__((aligned(16))) uint32_t lds1[ST3];
   int ti, tj, jw;
   decode_tile<OUT>(g, ti, tj, jw);
   const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
@@ -1562,40 +1597,28 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
 
   const int aoff = lane_off3(h, wm * 64 + l32);
   const int boff = (6 + 6 * half) * HWD + lane_off3(h, c0 + l32);
-  stage_dma3(lds, g, Ap, B0, B1, 0, w, lane);
-  for (int st = 0; st < g.nst; ++st) {
+  stage_dma3(lds0, g, Ap, B0, B1, 0, w, lane);
+  for (int st = 0; st < g.nst; st += 2) {
     wait_vm0();
     lds_barrier();
-    if (st + 1 < g.nst) stage_dma3(lds + ((st + 1) & 1) * ST3, g, Ap, B0, B1, st + 1, w, lane);
-    const uint32_t* L = lds + (st & 1) * ST3;
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      uint4 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        ah[rb] = *reinterpret_cast<const uint4*>(L + (2 * p) * HWD + aoff + rb * 128);
-        al[rb] = *reinterpret_cast<const uint4*>(L + (2 * p + 1) * HWD + aoff + rb * 128);
-      }
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        bh[cb] = *reinterpret_cast<const uint4*>(L + boff + (2 * p) * HWD + cb * 128);
-        bl[cb] = *reinterpret_cast<const uint4*>(L + boff + (2 * p + 1) * HWD + cb * 128);
-      }
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          t[p][rb][cb] = mma3<W>(ah[rb], bh[cb], t[p][rb][cb]);
-          t[p][rb][cb] = mma3<W>(ah[rb], bl[cb], t[p][rb][cb]);
-          t[p][rb][cb] = mma3<W>(al[rb], bh[cb], t[p][rb][cb]);
-        }
+    if (st + 1 < g.nst) stage_dma3(lds1, g, Ap, B0, B1, st + 1, w, lane);
+    stage_mma3<W>(lds0, aoff, boff, t);
+    if (st + 1 < g.nst) {
+      wait_vm0();
+      lds_barrier();
+      if (st + 2 < g.nst) stage_dma3(lds0, g, Ap, B0, B1, st + 2, w, lane);
+      stage_mma3<W>(lds1, aoff, boff, t);
     }
   }
   __syncthreads();   // every wave is done with the last stage's LDS
 
   const float sg = g.sigma3;
   if constexpr (OUT == OUT_HERK) {
-    float2* E = reinterpret_cast<float2*>(lds);
+    // 128 x 128 staging of one column half: rows 0..63 in the first stage
+    // buffer, rows 64..127 in the second (64 KB each).
+    float2* E0 = reinterpret_cast<float2*>(lds0);
+    float2* E1 = reinterpret_cast<float2*>(lds1);
+    float2* Ew = wm ? E1 : E0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       if (half == c) {
@@ -1605,14 +1628,14 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
           for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-              const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+              const int lr = rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3), row = wm * 64 + lr;
               const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
               float un = 1.f;
               if constexpr (W == 1) {
                 const float* sj = g.sa + (size_t)jw * g.s_stride;
                 un = 1.f / (sj[ti * TM + row] * sj[tj * TN + c * 128 + c0 + cb * 32 + l32]);
               }
-              E[row * 128 + c0 + cb * 32 + l32] = make_float2((t1 + sg * t2) * un, (t3 - t1 + sg * t2) * un);
+              Ew[lr * 128 + c0 + cb * 32 + l32] = make_float2((t1 + sg * t2) * un, (t3 - t1 + sg * t2) * un);
             }
       }
       __syncthreads();
@@ -1621,7 +1644,7 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
       for (int e = tid; e < 128 * 128; e += GT8) {
         const int gi = ti * TM + (e >> 7), gj = tj * TN + c * 128 + (e & 127);
         if (gi < g.N && gj <= gi) {
-          const float2 x = E[e];
+          const float2 x = e < 64 * 128 ? E0[e] : E1[e - 64 * 128];
           double2* pp = Pj + (size_t)gi * g.N + gj;
           double2 y = *pp;
           y.x -= (double)x.x;
@@ -1767,14 +1790,8 @@ int launch_gemm8(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
 
 template <int OUT, int W>
 int launch_gemm3m(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
-  static int attr = 0;
-  if (!attr) {
-    GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm3m_kernel<OUT, W>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemm3Lds));
-    attr = 1;
-  }
-  ProfScope prof(s, name);
-  hipLaunchKernelGGL((gemm3m_kernel<OUT, W>), dim3(grid), dim3(GT8), kGemm3Lds, s, a);
+  ProfScope prof(s, name);  // the two 72 KB stage buffers are static LDS
+  hipLaunchKernelGGL((gemm3m_kernel<OUT, W>), dim3(grid), dim3(GT8), 0, s, a);
   GW_LAUNCHED("gemm3m_kernel");
   return GW_OK;
 }
