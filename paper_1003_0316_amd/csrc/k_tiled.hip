@@ -1543,82 +1543,52 @@ __device__ inline floatx16 mma3(uint4 a, uint4 b, floatx16 c) {
                                                   0, 0);
 }
 
-// The 36 MFMAs of one stage from LDS buffer L.
+// The 12 MFMAs of one plane: A plane words at A (hi) and A + HWD (lo), B
+// plane words at B and B + HWD, both already offset to this lane's rows.
+template <int W>
+__device__ __forceinline__ void plane_mma3(const uint32_t* A, const uint32_t* B, floatx16 (&t)[2][2]) {
+  uint4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+    ah[rb] = *reinterpret_cast<const uint4*>(A + rb * 128);
+    al[rb] = *reinterpret_cast<const uint4*>(A + HWD + rb * 128);
+  }
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    bh[cb] = *reinterpret_cast<const uint4*>(B + cb * 128);
+    bl[cb] = *reinterpret_cast<const uint4*>(B + HWD + cb * 128);
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      t[rb][cb] = mma3<W>(ah[rb], bh[cb], t[rb][cb]);
+      t[rb][cb] = mma3<W>(ah[rb], bl[cb], t[rb][cb]);
+      t[rb][cb] = mma3<W>(al[rb], bh[cb], t[rb][cb]);
+    }
+}
+
+// The 36 MFMAs of one stage from stage buffer L (A plane words 0..5, then the
+// B halves' plane words from 6 and 12).
 template <int W>
 __device__ __forceinline__ void stage_mma3(const uint32_t* L, int aoff, int boff, floatx16 (&t)[3][2][2]) {
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    uint4 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      ah[rb] = *reinterpret_cast<const uint4*>(L + (2 * p) * HWD + aoff + rb * 128);
-      al[rb] = *reinterpret_cast<const uint4*>(L + (2 * p + 1) * HWD + aoff + rb * 128);
-    }
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      bh[cb] = *reinterpret_cast<const uint4*>(L + boff + (2 * p) * HWD + cb * 128);
-      bl[cb] = *reinterpret_cast<const uint4*>(L + boff + (2 * p + 1) * HWD + cb * 128);
-    }
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        t[p][rb][cb] = mma3<W>(ah[rb], bh[cb], t[p][rb][cb]);
-        t[p][rb][cb] = mma3<W>(ah[rb], bl[cb], t[p][rb][cb]);
-        t[p][rb][cb] = mma3<W>(al[rb], bh[cb], t[p][rb][cb]);
-      }
-  }
+  for (int p = 0; p < 3; ++p) plane_mma3<W>(L + (2 * p) * HWD + aoff, L + boff + (2 * p) * HWD, t[p]);
 }
 
-template <int OUT, int W>
-__global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint32_t lds0[ST3];
-  __shared__ __attribute__((aligned(16))) uint32_t lds1[ST3];
-  int ti, tj, jw;
-  decode_tile<OUT>(g, ti, tj, jw);
-  const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
-  const uint32_t* B0 = g.B + jw * g.omega_stride + (size_t)(2 * tj) * g.b_bstride;
-  const uint32_t* B1 = B0 + g.b_bstride;
-
-  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+// Combination of T1, T2, T3 into the complex result and the store: the
+// projection's tiled or row-major M, or the lower-triangle update of P for
+// the accumulation, staged through LDS one 128 x 128 column half at a time
+// (erow(r) points at staging row r, 128 float2).
+template <int OUT, int W, class ERow>
+__device__ __forceinline__ void epilogue3(const GemmArgs& g, const floatx16 (&t)[3][2][2], int ti, int tj, int jw,
+                                          int tid, ERow erow) {
+  const int lane = tid & 63, w = tid >> 6;
   const int wm = w >> 2, wn = w & 3;
   const int half = wn >> 1, c0 = (wn & 1) * 64;
   const int l32 = lane & 31, h = lane >> 5;
-
-  floatx16 t[3][2][2];
-#pragma unroll
-  for (int p = 0; p < 3; ++p)
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) t[p][a][b][v] = 0.f;
-
-  const int aoff = lane_off3(h, wm * 64 + l32);
-  const int boff = (6 + 6 * half) * HWD + lane_off3(h, c0 + l32);
-  stage_dma3(lds0, g, Ap, B0, B1, 0, w, lane);
-  for (int st = 0; st < g.nst; st += 2) {
-    wait_vm0();
-    lds_barrier();
-    if (st + 1 < g.nst) stage_dma3(lds1, g, Ap, B0, B1, st + 1, w, lane);
-    stage_mma3<W>(lds0, aoff, boff, t);
-    if (st + 1 < g.nst) {
-      wait_vm0();
-      lds_barrier();
-      if (st + 2 < g.nst) stage_dma3(lds0, g, Ap, B0, B1, st + 2, w, lane);
-      stage_mma3<W>(lds1, aoff, boff, t);
-    }
-  }
-  __syncthreads();   // every wave is done with the last stage's LDS
-
   const float sg = g.sigma3;
   if constexpr (OUT == OUT_HERK) {
-    // 128 x 128 staging of one column half: rows 0..63 in the first stage
-    // buffer, rows 64..127 in the second (64 KB each).
-    float2* E0 = reinterpret_cast<float2*>(lds0);
-    float2* E1 = reinterpret_cast<float2*>(lds1);
-    float2* Ew = wm ? E1 : E0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       if (half == c) {
@@ -1628,14 +1598,14 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
           for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-              const int lr = rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3), row = wm * 64 + lr;
+              const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
               const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
               float un = 1.f;
               if constexpr (W == 1) {
                 const float* sj = g.sa + (size_t)jw * g.s_stride;
                 un = 1.f / (sj[ti * TM + row] * sj[tj * TN + c * 128 + c0 + cb * 32 + l32]);
               }
-              Ew[lr * 128 + c0 + cb * 32 + l32] = make_float2((t1 + sg * t2) * un, (t3 - t1 + sg * t2) * un);
+              erow(row)[c0 + cb * 32 + l32] = make_float2((t1 + sg * t2) * un, (t3 - t1 + sg * t2) * un);
             }
       }
       __syncthreads();
@@ -1644,7 +1614,7 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
       for (int e = tid; e < 128 * 128; e += GT8) {
         const int gi = ti * TM + (e >> 7), gj = tj * TN + c * 128 + (e & 127);
         if (gi < g.N && gj <= gi) {
-          const float2 x = e < 64 * 128 ? E0[e] : E1[e - 64 * 128];
+          const float2 x = erow(e >> 7)[e & 127];
           double2* pp = Pj + (size_t)gi * g.N + gj;
           double2 y = *pp;
           y.x -= (double)x.x;
@@ -1678,6 +1648,164 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
           if (gi < g.N && gt < g.T) g.M[(size_t)gi * g.ldm + gt] = make_float2(re, im);
         }
       }
+}
+
+__device__ __forceinline__ void zero_acc3(floatx16 (&t)[3][2][2]) {
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) t[p][a][b][v] = 0.f;
+}
+
+// Two stage buffers of 72 KB: stage st + 1 is copied while stage st is
+// multiplied.
+template <int OUT, int W>
+__global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds0[ST3];
+  __shared__ __attribute__((aligned(16))) uint32_t lds1[ST3];
+  int ti, tj, jw;
+  decode_tile<OUT>(g, ti, tj, jw);
+  const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
+  const uint32_t* B0 = g.B + jw * g.omega_stride + (size_t)(2 * tj) * g.b_bstride;
+  const uint32_t* B1 = B0 + g.b_bstride;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w >> 2, wn = w & 3;
+  const int half = wn >> 1, c0 = (wn & 1) * 64;
+  const int l32 = lane & 31, h = lane >> 5;
+
+  floatx16 t[3][2][2];
+  zero_acc3(t);
+  const int aoff = lane_off3(h, wm * 64 + l32);
+  const int boff = (6 + 6 * half) * HWD + lane_off3(h, c0 + l32);
+  stage_dma3(lds0, g, Ap, B0, B1, 0, w, lane);
+  for (int st = 0; st < g.nst; st += 2) {
+    wait_vm0();
+    lds_barrier();
+    if (st + 1 < g.nst) stage_dma3(lds1, g, Ap, B0, B1, st + 1, w, lane);
+    stage_mma3<W>(lds0, aoff, boff, t);
+    if (st + 1 < g.nst) {
+      wait_vm0();
+      lds_barrier();
+      if (st + 2 < g.nst) stage_dma3(lds0, g, Ap, B0, B1, st + 2, w, lane);
+      stage_mma3<W>(lds1, aoff, boff, t);
+    }
+  }
+  __syncthreads();   // every wave is done with the last stage's LDS
+
+  // staging rows 0..63 in the first stage buffer, 64..127 in the second
+  float2* E0 = reinterpret_cast<float2*>(lds0);
+  float2* E1 = reinterpret_cast<float2*>(lds1);
+  epilogue3<OUT, W>(g, t, ti, tj, jw, tid, [&](int r) { return r < 64 ? E0 + r * 128 : E1 + (r - 64) * 128; });
+}
+
+// ------------------------------------------------ six-slot ring of the core
+// The same tile, operands and epilogue with finer staging: the LDS holds six
+// plane slots of 24 KB (one plane's hi and lo words of A and of both B
+// halves), and plane step i (stage i / 3, plane i % 3) is copied five plane
+// steps before it is multiplied, against three in the two-buffer form, at one
+// barrier per plane step instead of one per stage.  Every plane step issues
+// exactly three copies per wave (past the last step: the last step's source
+// again, into a slot that is not read any more), so the copy of step i is
+// complete once at most 12 copies of this wave are outstanding.
+constexpr int SL3 = 6 * HWD;  // dwords per plane slot (24 KB)
+
+// Copy of plane p of stage st into slot S: chunk w of each of the slot's
+// three regions (A, first B half, second B half), i.e. plane word
+// 2p + (w >> 2), quarter w & 3.
+__device__ __forceinline__ void slot_dma3(uint32_t* S, const GemmArgs& g, const uint32_t* Ap, const uint32_t* B0,
+                                          const uint32_t* B1, int st, int p, int w, int lane) {
+  const size_t a_step = (size_t)g.a_words3 * HWD, b_step = (size_t)g.b_words3 * HWD;
+  const int pw = 2 * p + (w >> 2), q = (w & 3) * 256 + lane * 4;
+  const int bplane = pw < 4 ? pw : g.b_sum3 + (pw - 4);
+  const size_t bo = (size_t)st * b_step + (size_t)bplane * HWD + q;
+  __builtin_amdgcn_global_load_lds(Ap + (size_t)st * a_step + (size_t)pw * HWD + q, (lds_void*)(S + w * 256), 16, 0,
+                                   0);
+  __builtin_amdgcn_global_load_lds(B0 + bo, (lds_void*)(S + 2 * HWD + w * 256), 16, 0, 0);
+  __builtin_amdgcn_global_load_lds(B1 + bo, (lds_void*)(S + 4 * HWD + w * 256), 16, 0, 0);
+}
+
+// s_waitcnt vmcnt(12) (expcnt and lgkmcnt left at their maxima).
+__device__ __forceinline__ void wait_vm12() { __builtin_amdgcn_s_waitcnt(0x0F7C); }
+
+// Workgroup barrier between plane steps.  The acquire fences keep this wave's
+// reads of the previous step above the barrier and the next copy below it; a
+// release fence is not needed (the only LDS writes are the copies, waited for
+// explicitly) and would make the compiler wait for every copy in flight.
+__device__ __forceinline__ void ring_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int OUT, int W>
+__global__ __launch_bounds__(GT8, 1) void gemm3r_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint32_t s0[SL3];
+  __shared__ __attribute__((aligned(16))) uint32_t s1[SL3];
+  __shared__ __attribute__((aligned(16))) uint32_t s2[SL3];
+  __shared__ __attribute__((aligned(16))) uint32_t s3[SL3];
+  __shared__ __attribute__((aligned(16))) uint32_t s4[SL3];
+  __shared__ __attribute__((aligned(16))) uint32_t s5[SL3];
+  uint32_t* const Q[6] = {s0, s1, s2, s3, s4, s5};
+  int ti, tj, jw;
+  decode_tile<OUT>(g, ti, tj, jw);
+  const uint32_t* Ap = g.A + jw * g.omega_stride + ti * g.a_bstride;
+  const uint32_t* B0 = g.B + jw * g.omega_stride + (size_t)(2 * tj) * g.b_bstride;
+  const uint32_t* B1 = B0 + g.b_bstride;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w >> 2, wn = w & 3;
+  const int half = wn >> 1, c0 = (wn & 1) * 64;
+  const int l32 = lane & 31, h = lane >> 5;
+
+  floatx16 t[3][2][2];
+  zero_acc3(t);
+  const int aoff = lane_off3(h, wm * 64 + l32);
+  const int boff = (2 + 2 * half) * HWD + lane_off3(h, c0 + l32);
+  const int steps = 3 * g.nst;
+  auto issue = [&](int j, uint32_t* S) {
+    j = min(j, steps - 1);
+    slot_dma3(S, g, Ap, B0, B1, j / 3, j % 3, w, lane);
+  };
+#pragma unroll
+  for (int k = 0; k < 5; ++k) issue(k, Q[k]);
+  int i = 0;
+  for (; i + 6 <= steps; i += 6) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      wait_vm12();
+      ring_barrier();
+      issue(i + k + 5, Q[(k + 5) % 6]);
+      plane_mma3<W>(Q[k] + aoff, Q[k] + boff, t[k % 3]);
+    }
+  }
+  if (i < steps) {   // steps is a multiple of 3: one stage left
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      wait_vm12();
+      ring_barrier();
+      issue(i + k + 5, Q[(k + 5) % 6]);
+      plane_mma3<W>(Q[k] + aoff, Q[k] + boff, t[k]);
+    }
+  }
+  wait_vm0();
+  __syncthreads();   // copies landed, every wave is done with the slots
+
+  // staging row r in slot r / 24 (24 rows of 128 float2 per slot)
+  epilogue3<OUT, W>(g, t, ti, tj, jw, tid, [](int r) {
+    const int k = r / 24;
+    uint32_t* p = s0;
+    p = k == 1 ? s1 : p;
+    p = k == 2 ? s2 : p;
+    p = k == 3 ? s3 : p;
+    p = k == 4 ? s4 : p;
+    p = k == 5 ? s5 : p;
+    return reinterpret_cast<float2*>(p) + (r - 24 * k) * 128;
+  });
 }
 
 template <int OUT>
@@ -1790,7 +1918,12 @@ int launch_gemm8(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
 
 template <int OUT, int W>
 int launch_gemm3m(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
-  ProfScope prof(s, name);  // the two 72 KB stage buffers are static LDS
+  ProfScope prof(s, name);  // stage buffers and slots are static LDS
+  if (g_gemm3m_pipeline == 6) {
+    hipLaunchKernelGGL((gemm3r_kernel<OUT, W>), dim3(grid), dim3(GT8), 0, s, a);
+    GW_LAUNCHED("gemm3r_kernel");
+    return GW_OK;
+  }
   hipLaunchKernelGGL((gemm3m_kernel<OUT, W>), dim3(grid), dim3(GT8), 0, s, a);
   GW_LAUNCHED("gemm3m_kernel");
   return GW_OK;

@@ -151,7 +151,7 @@ def test_tuning_switches_validate(b):
     L = b.lib()
     for key, lo, hi, default in (("bf16_pipeline", 1, 2, 2), ("projection_variant", 1, 2, 2),
                                  ("gemm_staging", 1, 4, 3), ("complex_product", 3, 4, 3),
-                                 ("fp16_core", 1, 2, 1)):
+                                 ("fp16_core", 1, 2, 1), ("gemm3m_pipeline", 2, 6, 6)):
         assert b.gw_get_tuning(key) == default
         for v in (lo, hi):
             assert L.gw_set_tuning(key.encode(), v) == 0
@@ -159,6 +159,7 @@ def test_tuning_switches_validate(b):
             assert L.gw_set_tuning(key.encode(), v) == -1
             assert key in L.gw_last_error().decode()
         assert L.gw_set_tuning(key.encode(), default) == 0
+    assert L.gw_set_tuning(b"gemm3m_pipeline", 4) == -1   # two stage buffers or six plane slots only
     assert L.gw_set_tuning(b"no_such_key", 1) == -1
     assert L.gw_set_tuning(None, 1) == -1
     v = ctypes.c_int(0)

@@ -252,6 +252,43 @@ def test_three_product_core(lib, shape):
         assert np.array_equal(Pg[j], Pg[j].conj().T)
 
 
+@pytest.mark.parametrize("shape", [
+    dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150),    # 63 K stages: the six-slot ring's tail
+    dict(n_k=1, n_b=20, R=33, N=7, n_occ=1, n_unocc=5),          # 3 stages: fewer than the ring's depth
+    dict(n_k=3, n_b=64, R=512, N=129, n_occ=2, n_unocc=63),      # 32 stages
+])
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_three_product_core_pipelines_bitwise(lib, shape, prec):
+    """The two staging schemes of the three-multiplication core (two 72 KB
+    stage buffers; six 24 KB plane slots copied five plane steps ahead, the
+    default) issue
+    the same MFMAs in the same order on every accumulator, so P and M agree
+    bit for bit; the slot ring also meets the reduced-precision bar against
+    the oracle.  Split FP16 runs on the three-product core (fp16_core 2)."""
+    import torch
+    inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=21, omega=gwsynth.omega_mesh("m16"))
+    U, psi = _dev(inp)
+    n_occ = shape["n_occ"]
+    out = {}
+    try:
+        lib.gw_set_tuning("fp16_core", 2)
+        for pipe in (2, 6):
+            lib.gw_set_tuning("gemm3m_pipeline", pipe)
+            P = lib.gw_polarization(U, psi, inp.eps, inp.omega, n_occ, precision=prec, kq=inp.kq)
+            M = lib.gw_project(U, psi[0, :n_occ].contiguous(), psi[0, n_occ:].contiguous(), prec)
+            torch.cuda.synchronize()
+            out[pipe] = (P.cpu().numpy(), M.cpu().numpy())
+    finally:
+        lib.gw_set_tuning("gemm3m_pipeline", 6)
+        lib.gw_set_tuning("fp16_core", 1)
+    assert np.array_equal(out[2][0], out[6][0]) and np.array_equal(out[2][1], out[6][1])
+    Ur, pr = _rounded(inp)
+    ref = orc.polarization(Ur, pr, inp.eps, inp.omega, n_occ, kq=inp.kq)
+    err = orc.rel_fro(out[6][0], ref)
+    print(f"three-product core, six-slot ring, {prec} {shape}: P max rel err {err.max():.2e}")
+    assert err.max() < TOL
+
+
 @pytest.mark.parametrize("core", [1, 2])
 def test_split_fp16_cores(lib, core):
     """Split FP16 on both kernel families: the operands staged inside the GEMM
