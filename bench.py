@@ -515,9 +515,10 @@ def summarize_pmc(a) -> int:
         wb = write.get(k, 0.0) * 1024.0 * (kw or 1.0)
         out["kernels"][k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
     # the projection runs as the OUT_TILED instance (first template argument 0)
-    # of the split-BF16 GEMM core: three-multiplication (gemm3m_), or 4-wave
-    # (gemm_) / 8-wave (gemm8_) four-product
-    dom = next((k for k in out["kernels"] if re.match(r"(gemm3m|gemm8?_bf16x3)_kernel<0[,>]", k)), None)
+    # of the split-BF16 GEMM core: three-multiplication (gemm3r_: six plane
+    # slots, gemm3m_: two stage buffers), or 4-wave (gemm_) / 8-wave (gemm8_)
+    # four-product
+    dom = next((k for k in out["kernels"] if re.match(r"(gemm3[rm]|gemm8?_bf16x3)_kernel<0[,>]", k)), None)
     if dom:
         out["kernel"] = "project_bf16_kernel"
         out["symbol"] = dom

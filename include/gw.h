@@ -443,11 +443,14 @@ int gw_sigma_c(void* stream, const gw_sigma_desc* d_host, void* ws, size_t ws_by
  *                         complex product (the gemm_staging variants above).
  *   "gemm3m_pipeline"     staging of the three-multiplication core: 6
  *                         (default): six 24 KB LDS slots, one plane (hi and lo
- *                         words of A and of both B halves) each, copied five
- *                         plane steps before use, one barrier per plane step;
- *                         2: two 72 KB stage buffers, the next stage copied
- *                         while the current one is multiplied, one barrier
- *                         per stage.  Same results bit for bit.
+ *                         words of A and of both B halves) each, copied
+ *                         gemm3m_lead plane steps before use, one barrier per
+ *                         plane step; 2: two 72 KB stage buffers, the next
+ *                         stage copied while the current one is multiplied,
+ *                         one barrier per stage.  Same results bit for bit.
+ *   "gemm3m_lead"         six-slot staging: 3, 4 (default) or 5 plane steps
+ *                         between a slot's copy and its use.  Same results
+ *                         bit for bit.
  * Values out of range and unknown keys give GW_ERR_INVALID_ARG.  Not
  * thread-safe: set before launching work.  gw_get_tuning reads a key's
  * current value. */

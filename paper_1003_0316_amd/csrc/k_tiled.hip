@@ -1578,8 +1578,10 @@ __device__ __forceinline__ void stage_mma3(const uint32_t* L, int aoff, int boff
 
 // Combination of T1, T2, T3 into the complex result and the store: the
 // projection's tiled or row-major M, or the lower-triangle update of P for
-// the accumulation, staged through LDS one 128 x 128 column half at a time
-// (erow(r) points at staging row r, 128 float2).
+// the accumulation, either staged through LDS one 128 x 128 column half at a
+// time (erow(r) points at staging row r, 128 float2) or, with erow null,
+// read-modified-written by each lane from its registers (32 consecutive
+// columns of one row per half wave).
 template <int OUT, int W, class ERow>
 __device__ __forceinline__ void epilogue3(const GemmArgs& g, const floatx16 (&t)[3][2][2], int ti, int tj, int jw,
                                           int tid, ERow erow) {
@@ -1588,7 +1590,31 @@ __device__ __forceinline__ void epilogue3(const GemmArgs& g, const floatx16 (&t)
   const int half = wn >> 1, c0 = (wn & 1) * 64;
   const int l32 = lane & 31, h = lane >> 5;
   const float sg = g.sigma3;
-  if constexpr (OUT == OUT_HERK) {
+  if constexpr (OUT == OUT_HERK && std::is_same<ERow, std::nullptr_t>::value) {
+    double2* Pj = g.P + (size_t)jw * g.N * g.N;
+    const float* sj = W == 1 ? g.sa + (size_t)jw * g.s_stride : nullptr;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          const int col = wn * 64 + cb * 32 + l32;
+          const int gi = ti * TM + row, gj = tj * TN + col;
+          if (gi < g.N && gj <= gi) {
+            const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
+            float un = 1.f;
+            if constexpr (W == 1) un = 1.f / (sj[gi] * sj[gj]);
+            double2* pp = Pj + (size_t)gi * g.N + gj;
+            double2 y = *pp;
+            y.x -= (double)((t1 + sg * t2) * un);
+            y.y -= (double)((t3 - t1 + sg * t2) * un);
+            *pp = y;
+          }
+        }
+    return;
+  } else if constexpr (OUT == OUT_HERK) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       if (half == c) {
@@ -1706,12 +1732,14 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
 // ------------------------------------------------ six-slot ring of the core
 // The same tile, operands and epilogue with finer staging: the LDS holds six
 // plane slots of 24 KB (one plane's hi and lo words of A and of both B
-// halves), and plane step i (stage i / 3, plane i % 3) is copied five plane
-// steps before it is multiplied, against three in the two-buffer form, at one
-// barrier per plane step instead of one per stage.  Every plane step issues
-// exactly three copies per wave (past the last step: the last step's source
-// again, into a slot that is not read any more), so the copy of step i is
-// complete once at most 12 copies of this wave are outstanding.
+// halves), and plane step i (stage i / 3, plane i % 3) is copied LEAD plane
+// steps before it is multiplied (at most five: the slot it lands in was read
+// at step i + LEAD - 6, before this step's barrier), against three in the
+// two-buffer form, at one barrier per plane step instead of one per stage.
+// Every plane step issues exactly three copies per wave (past the last step:
+// the last step's source again, into a slot that is not read any more), so
+// the copy of step i is complete once at most 3 (LEAD - 1) copies of this
+// wave are outstanding.
 constexpr int SL3 = 6 * HWD;  // dwords per plane slot (24 KB)
 
 // Copy of plane p of stage st into slot S: chunk w of each of the slot's
@@ -1729,8 +1757,12 @@ __device__ __forceinline__ void slot_dma3(uint32_t* S, const GemmArgs& g, const 
   __builtin_amdgcn_global_load_lds(B1 + bo, (lds_void*)(S + 4 * HWD + w * 256), 16, 0, 0);
 }
 
-// s_waitcnt vmcnt(12) (expcnt and lgkmcnt left at their maxima).
-__device__ __forceinline__ void wait_vm12() { __builtin_amdgcn_s_waitcnt(0x0F7C); }
+// s_waitcnt vmcnt(N), N < 16 (expcnt and lgkmcnt left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
 
 // Workgroup barrier between plane steps.  The acquire fences keep this wave's
 // reads of the previous step above the barrier and the next copy below it; a
@@ -1742,8 +1774,9 @@ __device__ __forceinline__ void ring_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int OUT, int W>
+template <int OUT, int W, int LEAD>
 __global__ __launch_bounds__(GT8, 1) void gemm3r_kernel(GemmArgs g) {
+  static_assert(LEAD >= 3 && LEAD <= 5, "slot (i + LEAD) % 6 must be free at plane step i");
   __shared__ __attribute__((aligned(16))) uint32_t s0[SL3];
   __shared__ __attribute__((aligned(16))) uint32_t s1[SL3];
   __shared__ __attribute__((aligned(16))) uint32_t s2[SL3];
@@ -1772,40 +1805,29 @@ __global__ __launch_bounds__(GT8, 1) void gemm3r_kernel(GemmArgs g) {
     slot_dma3(S, g, Ap, B0, B1, j / 3, j % 3, w, lane);
   };
 #pragma unroll
-  for (int k = 0; k < 5; ++k) issue(k, Q[k]);
+  for (int k = 0; k < LEAD; ++k) issue(k, Q[k]);
   int i = 0;
   for (; i + 6 <= steps; i += 6) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      wait_vm12();
+      wait_vm<3 * (LEAD - 1)>();
       ring_barrier();
-      issue(i + k + 5, Q[(k + 5) % 6]);
+      issue(i + k + LEAD, Q[(k + LEAD) % 6]);
       plane_mma3<W>(Q[k] + aoff, Q[k] + boff, t[k % 3]);
     }
   }
   if (i < steps) {   // steps is a multiple of 3: one stage left
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      wait_vm12();
+      wait_vm<3 * (LEAD - 1)>();
       ring_barrier();
-      issue(i + k + 5, Q[(k + 5) % 6]);
+      issue(i + k + LEAD, Q[(k + LEAD) % 6]);
       plane_mma3<W>(Q[k] + aoff, Q[k] + boff, t[k]);
     }
   }
-  wait_vm0();
-  __syncthreads();   // copies landed, every wave is done with the slots
+  wait_vm0();        // no copy into LDS outstanding at exit
 
-  // staging row r in slot r / 24 (24 rows of 128 float2 per slot)
-  epilogue3<OUT, W>(g, t, ti, tj, jw, tid, [](int r) {
-    const int k = r / 24;
-    uint32_t* p = s0;
-    p = k == 1 ? s1 : p;
-    p = k == 2 ? s2 : p;
-    p = k == 3 ? s3 : p;
-    p = k == 4 ? s4 : p;
-    p = k == 5 ? s5 : p;
-    return reinterpret_cast<float2*>(p) + (r - 24 * k) * 128;
-  });
+  epilogue3<OUT, W>(g, t, ti, tj, jw, tid, nullptr);
 }
 
 template <int OUT>
@@ -1920,7 +1942,12 @@ template <int OUT, int W>
 int launch_gemm3m(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
   ProfScope prof(s, name);  // stage buffers and slots are static LDS
   if (g_gemm3m_pipeline == 6) {
-    hipLaunchKernelGGL((gemm3r_kernel<OUT, W>), dim3(grid), dim3(GT8), 0, s, a);
+    if (g_gemm3m_lead == 3)
+      hipLaunchKernelGGL((gemm3r_kernel<OUT, W, 3>), dim3(grid), dim3(GT8), 0, s, a);
+    else if (g_gemm3m_lead == 4)
+      hipLaunchKernelGGL((gemm3r_kernel<OUT, W, 4>), dim3(grid), dim3(GT8), 0, s, a);
+    else
+      hipLaunchKernelGGL((gemm3r_kernel<OUT, W, 5>), dim3(grid), dim3(GT8), 0, s, a);
     GW_LAUNCHED("gemm3r_kernel");
     return GW_OK;
   }

@@ -260,8 +260,8 @@ def test_three_product_core(lib, shape):
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
 def test_three_product_core_pipelines_bitwise(lib, shape, prec):
     """The two staging schemes of the three-multiplication core (two 72 KB
-    stage buffers; six 24 KB plane slots copied five plane steps ahead, the
-    default) issue
+    stage buffers; six 24 KB plane slots copied 3, 4 (the default) or 5
+    plane steps ahead) issue
     the same MFMAs in the same order on every accumulator, so P and M agree
     bit for bit; the slot ring also meets the reduced-precision bar against
     the oracle.  Split FP16 runs on the three-product core (fp16_core 2)."""
@@ -272,19 +272,22 @@ def test_three_product_core_pipelines_bitwise(lib, shape, prec):
     out = {}
     try:
         lib.gw_set_tuning("fp16_core", 2)
-        for pipe in (2, 6):
+        for pipe, lead in ((2, 4), (6, 3), (6, 4), (6, 5)):
             lib.gw_set_tuning("gemm3m_pipeline", pipe)
+            lib.gw_set_tuning("gemm3m_lead", lead)
             P = lib.gw_polarization(U, psi, inp.eps, inp.omega, n_occ, precision=prec, kq=inp.kq)
             M = lib.gw_project(U, psi[0, :n_occ].contiguous(), psi[0, n_occ:].contiguous(), prec)
             torch.cuda.synchronize()
-            out[pipe] = (P.cpu().numpy(), M.cpu().numpy())
+            out[pipe, lead] = (P.cpu().numpy(), M.cpu().numpy())
     finally:
         lib.gw_set_tuning("gemm3m_pipeline", 6)
+        lib.gw_set_tuning("gemm3m_lead", 4)
         lib.gw_set_tuning("fp16_core", 1)
-    assert np.array_equal(out[2][0], out[6][0]) and np.array_equal(out[2][1], out[6][1])
+    for key in ((6, 3), (6, 4), (6, 5)):
+        assert np.array_equal(out[2, 4][0], out[key][0]) and np.array_equal(out[2, 4][1], out[key][1]), key
     Ur, pr = _rounded(inp)
     ref = orc.polarization(Ur, pr, inp.eps, inp.omega, n_occ, kq=inp.kq)
-    err = orc.rel_fro(out[6][0], ref)
+    err = orc.rel_fro(out[6, 4][0], ref)
     print(f"three-product core, six-slot ring, {prec} {shape}: P max rel err {err.max():.2e}")
     assert err.max() < TOL
 
