@@ -451,6 +451,11 @@ int gw_sigma_c(void* stream, const gw_sigma_desc* d_host, void* ws, size_t ws_by
  *   "gemm3m_lead"         six-slot staging: 3, 4 (default) or 5 plane steps
  *                         between a slot's copy and its use.  Same results
  *                         bit for bit.
+ *   "real_core"           real inputs (gw_pol_desc.real_inputs): 1: the
+ *                         8-wave core with operands staged through registers;
+ *                         2 (default): the six-slot core, a real stage of 32 k
+ *                         taken as two planes of 16 k into one accumulator
+ *                         set.  Same results bit for bit.
  * Values out of range and unknown keys give GW_ERR_INVALID_ARG.  Not
  * thread-safe: set before launching work.  gw_get_tuning reads a key's
  * current value. */

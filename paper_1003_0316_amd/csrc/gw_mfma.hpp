@@ -19,6 +19,7 @@ int mfma_polarization(hipStream_t s, const gw_pol_desc& d, const std::vector<Chu
 extern int g_bf16_pipeline;   // 1: operands staged inside the GEMM kernels; 2: pre-tiled operands
 extern int g_gemm_staging;    // pre-tiled GEMM core: 1 through registers, 2 direct global -> LDS
 extern int g_complex_product; // pre-tiled pipeline: 4 real products per complex product, or 3 (Gauss form)
+extern int g_real_core;       // real inputs: 1 the 8-wave register-staged core, 2 the six-slot core
 extern int g_gemm3m_lead;     // six-slot ring: plane steps between a slot's copy and its use (3..5)
 extern int g_gemm3m_pipeline; // three-product core staging: 2 stage buffers, or 6 plane slots
 extern int g_fp16_core;       // split FP16: 1 operands staged inside the GEMM kernels, 2 the three-product core

@@ -1019,6 +1019,7 @@ int g_complex_product = 3;
 int g_fp16_core = 1;
 int g_gemm3m_pipeline = 6;
 int g_gemm3m_lead = 4;
+int g_real_core = 2;
 
 static bool tiled_path(int precision) {
   return (precision == GW_SPLIT_BF16 && g_bf16_pipeline == 2) || (precision == GW_SPLIT_FP16 && g_fp16_core == 2);
@@ -1176,6 +1177,7 @@ extern "C" int gw_get_tuning(const char* key, int* value) {
   else if (k == "fp16_core") *value = gw::g_fp16_core;
   else if (k == "gemm3m_pipeline") *value = gw::g_gemm3m_pipeline;
   else if (k == "gemm3m_lead") *value = gw::g_gemm3m_lead;
+  else if (k == "real_core") *value = gw::g_real_core;
   else return gw::fail(GW_ERR_INVALID_ARG, std::string("gw_get_tuning: unknown key ") + key);
   return GW_OK;
 }
@@ -1196,6 +1198,11 @@ extern "C" int gw_set_tuning(const char* key, int value) {
   if (k == "fp16_core") {
     if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: fp16_core is 1 or 2");
     gw::g_fp16_core = value;
+    return GW_OK;
+  }
+  if (k == "real_core") {
+    if (value < 1 || value > 2) return gw::fail(GW_ERR_INVALID_ARG, "gw_set_tuning: real_core is 1 or 2");
+    gw::g_real_core = value;
     return GW_OK;
   }
   if (k == "gemm3m_lead") {

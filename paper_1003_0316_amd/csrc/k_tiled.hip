@@ -693,36 +693,60 @@ __global__ void tile_u_real_kernel(int N, int R, int nI, int nst, const float* _
   }
 }
 
-// Real pair products F_t = psi_n psi_n' -> B-side words [nT][nst][2][WD].
-__global__ void pair_product_real_kernel(int R, int nst, int nT, const float* __restrict__ po,
-                                         const float* __restrict__ pu, int nu, long tb, int T,
-                                         uint32_t* __restrict__ out) {
-  const size_t total = (size_t)nT * nst * 4 * TR;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int col = (int)(e % TR);
-    const int sh = (int)((e / TR) % 4);
-    const size_t bs = e / (4 * TR);
-    const int st = (int)(bs % nst), blk = (int)(bs / nst);
-    const int t = blk * TR + col;
-    const int r0 = st * 2 * TK + sh * 8;
-    const float* a = nullptr;
-    const float* b = nullptr;
+// Real pair products F_t = psi_n psi_n' -> B-side words [nT][nst][2][WD]
+// (pairs t >= T and k >= R zero).  Same two phases as the complex kernels: a
+// workgroup takes 128 pairs x 64 real k (two block-stages); 16 lanes read
+// each pair's two rows as 256-byte segments into an LDS tile, then lane =
+// pair, 8 k per item, 1 KB per store.
+constexpr int PPR_K = 4 * TK;              // real k per workgroup
+constexpr int PPR_PITCH = PPR_K + 1;       // odd pitch: 32 pair rows on distinct banks
+__global__ __launch_bounds__(256) void pair_product_real_kernel(int R, int nst, int nT, const float* __restrict__ po,
+                                                                const float* __restrict__ pu, int nu, long tb, int T,
+                                                                uint32_t* __restrict__ out) {
+  __shared__ float F[TR * PPR_PITCH];
+  const int blk = blockIdx.y;
+  const int st0 = blockIdx.x * 2;
+  const int tid = threadIdx.x;
+  const int r0 = st0 * 2 * TK;
+  const int sub = tid & 15, prow = tid >> 4;
+#pragma unroll
+  for (int pass = 0; pass < TR / 16; ++pass) {
+    const int p = pass * 16 + prow;
+    const int t = blk * TR + p;
+    const int r = r0 + 4 * sub;
+    float f[4] = {0.f, 0.f, 0.f, 0.f};
     if (t < T) {
       const long g = tb + t;
-      a = po + (size_t)(g / nu) * R;
-      b = pu + (size_t)(g % nu) * R;
-    }
-    uint32_t hw[4], lw[4];
+      const float* a = po + (size_t)(g / nu) * R;
+      const float* b = pu + (size_t)(g % nu) * R;
+      if (r + 3 < R && (R & 3) == 0) {
+        const float4 x = *reinterpret_cast<const float4*>(a + r);
+        const float4 y = *reinterpret_cast<const float4*>(b + r);
+        f[0] = x.x * y.x; f[1] = x.y * y.y; f[2] = x.z * y.z; f[3] = x.w * y.w;
+      } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = r0 + 2 * j;
-      const float f0 = (a && r < R) ? a[r] * b[r] : 0.f;
-      const float f1 = (a && r + 1 < R) ? a[r + 1] * b[r + 1] : 0.f;
-      split_pair(f0, f1, hw[j], lw[j]);
+        for (int j = 0; j < 4; ++j)
+          if (r + j < R) f[j] = a[r + j] * b[r + j];
+      }
     }
-    uint32_t* o = out + bs * 2 * WD + lane_off(sh, col);
-    *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-    *reinterpret_cast<uint4*>(o + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) F[p * PPR_PITCH + 4 * sub + j] = f[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < (TR * PPR_K / 8) / 256; ++it) {
+    const int item = it * 256 + tid;
+    const int p = item & (TR - 1), grp = item >> 7;   // grp 0..7: stage st0 + grp / 4, sub-half grp % 4
+    const int st = st0 + (grp >> 2);
+    if (st < nst) {
+      uint32_t hw[4], lw[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        split_pair(F[p * PPR_PITCH + grp * 8 + 2 * j], F[p * PPR_PITCH + grp * 8 + 2 * j + 1], hw[j], lw[j]);
+      uint32_t* o = out + ((size_t)blk * nst + st) * 2 * WD + lane_off(grp & 3, p);
+      *reinterpret_cast<uint4*>(o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      *reinterpret_cast<uint4*>(o + WD) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
   }
 }
 
@@ -1582,7 +1606,11 @@ __device__ __forceinline__ void stage_mma3(const uint32_t* L, int aoff, int boff
 // time (erow(r) points at staging row r, 128 float2) or, with erow null,
 // read-modified-written by each lane from its registers (32 consecutive
 // columns of one row per half wave).
-template <int OUT, int W, class ERow>
+//
+// REAL: real operands, the sum over k in t[0] alone; the result is that sum
+// (imaginary part zero), and the projection writes the real M layout the
+// real accumulation operands are made from ([nI][T/32][4][TR][8] floats).
+template <int OUT, int W, bool REAL = false, class ERow>
 __device__ __forceinline__ void epilogue3(const GemmArgs& g, const floatx16 (&t)[3][2][2], int ti, int tj, int jw,
                                           int tid, ERow erow) {
   const int lane = tid & 63, w = tid >> 6;
@@ -1590,6 +1618,7 @@ __device__ __forceinline__ void epilogue3(const GemmArgs& g, const floatx16 (&t)
   const int half = wn >> 1, c0 = (wn & 1) * 64;
   const int l32 = lane & 31, h = lane >> 5;
   const float sg = g.sigma3;
+  static_assert(!REAL || (W == 0 && std::is_same<ERow, std::nullptr_t>::value), "real operands: BF16, direct epilogue");
   if constexpr (OUT == OUT_HERK && std::is_same<ERow, std::nullptr_t>::value) {
     double2* Pj = g.P + (size_t)jw * g.N * g.N;
     const float* sj = W == 1 ? g.sa + (size_t)jw * g.s_stride : nullptr;
@@ -1603,13 +1632,17 @@ __device__ __forceinline__ void epilogue3(const GemmArgs& g, const floatx16 (&t)
           const int col = wn * 64 + cb * 32 + l32;
           const int gi = ti * TM + row, gj = tj * TN + col;
           if (gi < g.N && gj <= gi) {
-            const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
-            float un = 1.f;
-            if constexpr (W == 1) un = 1.f / (sj[gi] * sj[gj]);
             double2* pp = Pj + (size_t)gi * g.N + gj;
             double2 y = *pp;
-            y.x -= (double)((t1 + sg * t2) * un);
-            y.y -= (double)((t3 - t1 + sg * t2) * un);
+            if constexpr (REAL) {
+              y.x -= (double)t[0][rb][cb][v];
+            } else {
+              const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
+              float un = 1.f;
+              if constexpr (W == 1) un = 1.f / (sj[gi] * sj[gj]);
+              y.x -= (double)((t1 + sg * t2) * un);
+              y.y -= (double)((t3 - t1 + sg * t2) * un);
+            }
             *pp = y;
           }
         }
@@ -1660,11 +1693,23 @@ __device__ __forceinline__ void epilogue3(const GemmArgs& g, const floatx16 (&t)
       for (int v = 0; v < 16; ++v) {
         const int row = wm * 64 + rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         const int col = wn * 64 + cb * 32 + l32;
-        const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
-        float un = 1.f;
-        if constexpr (W == 1) un = 1.f / (g.sa[ti * TM + row] * g.sb[tj * TN + col]);
-        const float re = (t1 + sg * t2) * un, im = (t3 - t1 + sg * t2) * un;
-        if constexpr (OUT == OUT_TILED) {
+        float re, im;
+        if constexpr (REAL) {
+          re = t[0][rb][cb][v];
+          im = 0.f;
+        } else {
+          const float t1 = t[0][rb][cb][v], t2 = t[1][rb][cb][v], t3 = t[2][rb][cb][v];
+          float un = 1.f;
+          if constexpr (W == 1) un = 1.f / (g.sa[ti * TM + row] * g.sb[tj * TN + col]);
+          re = (t1 + sg * t2) * un;
+          im = (t3 - t1 + sg * t2) * un;
+        }
+        if constexpr (OUT == OUT_TILED && REAL) {
+          const int tt = tj * TN + col;
+          const size_t bs = (size_t)ti * g.nst_out + tt / (2 * TK);
+          const int kk = tt % (2 * TK);
+          reinterpret_cast<float*>(g.M)[((bs * 4 + (kk >> 3)) * TR + row) * 8 + (kk & 7)] = re;
+        } else if constexpr (OUT == OUT_TILED) {
           const int tt = tj * TN + col;
           const size_t bs = (size_t)ti * g.nst_out + tt / TK;
           const int kk = tt % TK;
@@ -1743,13 +1788,18 @@ __global__ __launch_bounds__(GT8, 1) void gemm3m_kernel(GemmArgs g) {
 constexpr int SL3 = 6 * HWD;  // dwords per plane slot (24 KB)
 
 // Copy of plane p of stage st into slot S: chunk w of each of the slot's
-// three regions (A, first B half, second B half), i.e. plane word
-// 2p + (w >> 2), quarter w & 3.
+// three regions (A, first B half, second B half), i.e. the hi (w < 4) or lo
+// word of the plane, quarter w & 3.  Complex planes: words 2p (hi), 2p + 1
+// (lo) of a stage of six (the B side's third plane from b_sum3 on).  REAL: a
+// stage is one real block-stage of 32 k, planes p = 0, 1 its two halves of
+// 16 k; hi words at p, lo words at 2 + p (four words per stage).
+template <bool REAL>
 __device__ __forceinline__ void slot_dma3(uint32_t* S, const GemmArgs& g, const uint32_t* Ap, const uint32_t* B0,
                                           const uint32_t* B1, int st, int p, int w, int lane) {
   const size_t a_step = (size_t)g.a_words3 * HWD, b_step = (size_t)g.b_words3 * HWD;
-  const int pw = 2 * p + (w >> 2), q = (w & 3) * 256 + lane * 4;
-  const int bplane = pw < 4 ? pw : g.b_sum3 + (pw - 4);
+  const int hl = w >> 2, q = (w & 3) * 256 + lane * 4;
+  const int pw = REAL ? p + 2 * hl : 2 * p + hl;
+  const int bplane = (REAL || pw < 4) ? pw : g.b_sum3 + (pw - 4);
   const size_t bo = (size_t)st * b_step + (size_t)bplane * HWD + q;
   __builtin_amdgcn_global_load_lds(Ap + (size_t)st * a_step + (size_t)pw * HWD + q, (lds_void*)(S + w * 256), 16, 0,
                                    0);
@@ -1774,9 +1824,10 @@ __device__ __forceinline__ void ring_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int OUT, int W, int LEAD>
+template <int OUT, int W, int LEAD, bool REAL = false>
 __global__ __launch_bounds__(GT8, 1) void gemm3r_kernel(GemmArgs g) {
   static_assert(LEAD >= 3 && LEAD <= 5, "slot (i + LEAD) % 6 must be free at plane step i");
+  constexpr int NP = REAL ? 2 : 3;   // planes per stage
   __shared__ __attribute__((aligned(16))) uint32_t s0[SL3];
   __shared__ __attribute__((aligned(16))) uint32_t s1[SL3];
   __shared__ __attribute__((aligned(16))) uint32_t s2[SL3];
@@ -1799,11 +1850,14 @@ __global__ __launch_bounds__(GT8, 1) void gemm3r_kernel(GemmArgs g) {
   zero_acc3(t);
   const int aoff = lane_off3(h, wm * 64 + l32);
   const int boff = (2 + 2 * half) * HWD + lane_off3(h, c0 + l32);
-  const int steps = 3 * g.nst;
+  const int steps = NP * g.nst;
   auto issue = [&](int j, uint32_t* S) {
     j = min(j, steps - 1);
-    slot_dma3(S, g, Ap, B0, B1, j / 3, j % 3, w, lane);
+    slot_dma3<REAL>(S, g, Ap, B0, B1, j / NP, j % NP, w, lane);
   };
+  // accumulator set of the plane at position k of a six-step group (real:
+  // one set, in k order)
+  auto acc = [&](int k) -> floatx16 (&)[2][2] { return t[REAL ? 0 : k % 3]; };
 #pragma unroll
   for (int k = 0; k < LEAD; ++k) issue(k, Q[k]);
   int i = 0;
@@ -1813,21 +1867,23 @@ __global__ __launch_bounds__(GT8, 1) void gemm3r_kernel(GemmArgs g) {
       wait_vm<3 * (LEAD - 1)>();
       ring_barrier();
       issue(i + k + LEAD, Q[(k + LEAD) % 6]);
-      plane_mma3<W>(Q[k] + aoff, Q[k] + boff, t[k % 3]);
+      plane_mma3<W>(Q[k] + aoff, Q[k] + boff, acc(k));
     }
   }
-  if (i < steps) {   // steps is a multiple of 3: one stage left
+  if (i < steps) {   // a multiple of NP steps is left: one stage (complex) or 1-2 stages (real)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      wait_vm<3 * (LEAD - 1)>();
-      ring_barrier();
-      issue(i + k + LEAD, Q[(k + LEAD) % 6]);
-      plane_mma3<W>(Q[k] + aoff, Q[k] + boff, t[k]);
+    for (int k = 0; k < 6 - NP; ++k) {
+      if (k < NP || i + k < steps) {
+        wait_vm<3 * (LEAD - 1)>();
+        ring_barrier();
+        issue(i + k + LEAD, Q[(k + LEAD) % 6]);
+        plane_mma3<W>(Q[k] + aoff, Q[k] + boff, acc(k));
+      }
     }
   }
   wait_vm0();        // no copy into LDS outstanding at exit
 
-  epilogue3<OUT, W>(g, t, ti, tj, jw, tid, nullptr);
+  epilogue3<OUT, W, REAL>(g, t, ti, tj, jw, tid, nullptr);
 }
 
 template <int OUT>
@@ -1953,6 +2009,20 @@ int launch_gemm3m(hipStream_t s, const GemmArgs& a, int grid, const char* name) 
   }
   hipLaunchKernelGGL((gemm3m_kernel<OUT, W>), dim3(grid), dim3(GT8), 0, s, a);
   GW_LAUNCHED("gemm3m_kernel");
+  return GW_OK;
+}
+
+// Six-slot core for real operands (inversion-symmetric inputs), BF16 words.
+template <int OUT>
+int launch_gemm3r_real(hipStream_t s, const GemmArgs& a, int grid, const char* name) {
+  ProfScope prof(s, name);
+  if (g_gemm3m_lead == 3)
+    hipLaunchKernelGGL((gemm3r_kernel<OUT, 0, 3, true>), dim3(grid), dim3(GT8), 0, s, a);
+  else if (g_gemm3m_lead == 4)
+    hipLaunchKernelGGL((gemm3r_kernel<OUT, 0, 4, true>), dim3(grid), dim3(GT8), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm3r_kernel<OUT, 0, 5, true>), dim3(grid), dim3(GT8), 0, s, a);
+  GW_LAUNCHED("gemm3r_kernel");
   return GW_OK;
 }
 
@@ -2316,8 +2386,8 @@ int tiled_polarization_real(hipStream_t s, const gw_pol_desc& d, const std::vect
     GW_LAUNCHED("weights_sqrt_kernel");
     {
       ProfScope prof(s, "pair_product_kernel");
-      hipLaunchKernelGGL(pair_product_real_kernel, dim3(stream_blocks((size_t)cd.nT * cd.nstR * 4 * TR)), dim3(256), 0,
-                         s, d.R, cd.nstR, cd.nT, po, pu, c.nu, c.tb, c.T, Q);
+      hipLaunchKernelGGL(pair_product_real_kernel, dim3((cd.nstR + 1) / 2, cd.nT), dim3(256), 0, s, d.R, cd.nstR,
+                         cd.nT, po, pu, c.nu, c.tb, c.T, Q);
       GW_LAUNCHED("pair_product_real_kernel");
     }
     GemmArgs a{};
@@ -2333,7 +2403,10 @@ int tiled_polarization_real(hipStream_t s, const gw_pol_desc& d, const std::vect
     a.T = c.T;
     a.M = reinterpret_cast<float2*>(Mt);
     a.nst_out = cd.nstT;
-    if ((st = launch_gemm8<OUT_TILED, true>(s, a, cd.nI * a.nTj, "project_bf16_kernel")) != GW_OK) return st;
+    a.a_words3 = a.b_words3 = 4;   // six-slot core: hi, hi, lo, lo plane words per real stage
+    if ((st = g_real_core == 2 ? launch_gemm3r_real<OUT_TILED>(s, a, cd.nI * a.nTj, "project_bf16_kernel")
+                               : launch_gemm8<OUT_TILED, true>(s, a, cd.nI * a.nTj, "project_bf16_kernel")) != GW_OK)
+      return st;
     {
       ProfScope prof(s, "scale_split_kernel");
       hipLaunchKernelGGL(scale_split_real_kernel, dim3(stream_blocks((size_t)cd.nIe * cd.nstT * 4 * TR)), dim3(256), 0,
@@ -2352,7 +2425,10 @@ int tiled_polarization_real(hipStream_t s, const gw_pol_desc& d, const std::vect
     b.n_tiles = n_tiles;
     b.N = d.N;
     b.P = reinterpret_cast<double2*>(d.P);
-    if ((st = launch_gemm8<OUT_HERK, true>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")) != GW_OK) return st;
+    b.a_words3 = b.b_words3 = 4;
+    if ((st = g_real_core == 2 ? launch_gemm3r_real<OUT_HERK>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")
+                               : launch_gemm8<OUT_HERK, true>(s, b, n_tiles * d.n_omega, "herk_bf16_kernel")) != GW_OK)
+      return st;
   }
   return GW_OK;
 }

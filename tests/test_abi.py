@@ -152,7 +152,7 @@ def test_tuning_switches_validate(b):
     for key, lo, hi, default in (("bf16_pipeline", 1, 2, 2), ("projection_variant", 1, 2, 2),
                                  ("gemm_staging", 1, 4, 3), ("complex_product", 3, 4, 3),
                                  ("fp16_core", 1, 2, 1), ("gemm3m_pipeline", 2, 6, 6),
-                                 ("gemm3m_lead", 3, 5, 4)):
+                                 ("gemm3m_lead", 3, 5, 4), ("real_core", 1, 2, 2)):
         assert b.gw_get_tuning(key) == default
         for v in (lo, hi):
             assert L.gw_set_tuning(key.encode(), v) == 0

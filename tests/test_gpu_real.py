@@ -79,3 +79,33 @@ def test_real_path_largest_size_sampled(lib):
     print(f"real path c5 shape: sampled max rel err {err.max():.2e}")
     assert err.max() < TOL
     assert np.all(Pg.imag == 0.0)
+
+
+@pytest.mark.parametrize("shape", [
+    dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150),   # 32 real K stages: the ring's 4-step tail
+    dict(n_k=3, n_b=64, R=513, N=129, n_occ=2, n_unocc=63),     # 17 stages: the 2-step tail
+    dict(n_k=1, n_b=20, R=33, N=7, n_occ=1, n_unocc=5),         # 2 stages: fewer steps than the copy lead
+])
+def test_real_cores_bitwise(lib, shape):
+    """The two real GEMM cores (the 8-wave register-staged core, real_core 1;
+    the six-slot core, real_core 2, the default, at leads 3 to 5) issue the
+    same MFMAs on every accumulator in the same order (hi hi, hi lo, lo hi per
+    16 k, k ascending), so P agrees bit for bit."""
+    import torch
+    inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=17, omega=gwsynth.omega_mesh("m16"))
+    U, psi = _real(inp)
+    Ud, pd = torch.from_numpy(U).to("cuda"), torch.from_numpy(psi).to("cuda")
+    out = {}
+    try:
+        for core, lead in ((1, 4), (2, 3), (2, 4), (2, 5)):
+            lib.gw_set_tuning("real_core", core)
+            lib.gw_set_tuning("gemm3m_lead", lead)
+            P = lib.gw_polarization(Ud, pd, inp.eps, inp.omega, shape["n_occ"], precision="split_bf16", kq=inp.kq,
+                                    real=True)
+            torch.cuda.synchronize()
+            out[core, lead] = P.cpu().numpy()
+    finally:
+        lib.gw_set_tuning("real_core", 2)
+        lib.gw_set_tuning("gemm3m_lead", 4)
+    for key in ((2, 3), (2, 4), (2, 5)):
+        assert np.array_equal(out[1, 4], out[key]), key
