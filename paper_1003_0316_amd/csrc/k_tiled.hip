@@ -620,6 +620,83 @@ __global__ void tile_cols_kernel(int N, int nb, int nTb, int nst, const float2* 
   }
 }
 
+// Operands of the self-energy's W^c M products for the three-multiplication
+// core.  W^c = W - diag(v) (c128 [N][N]) -> plane words [nI][nstN][6][HWD]:
+// re, im, re + im (hi, lo) of row I, k running over the columns of W^c;
+// zero for rows or columns >= N.
+__global__ void tile_wc3_kernel(int N, int nI, int nst, const double2* __restrict__ W, const double* __restrict__ v,
+                                uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nI * nst * 2 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % TR);
+    const int h = (int)((e / TR) % 2);
+    const size_t bs = e / (2 * TR);
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int I = blk * TR + row;
+    const int c0 = st * TK + 8 * h;
+    float re[8], im[8], sm[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double2 x = make_double2(0.0, 0.0);
+      const int c = c0 + q;
+      if (I < N && c < N) {
+        x = W[(size_t)I * N + c];
+        if (c == I) x.x -= v[I];
+      }
+      re[q] = (float)x.x;
+      im[q] = (float)x.y;
+      sm[q] = re[q] + im[q];
+    }
+    uint32_t* o = out + bs * 6 * HWD + lane_off3(h, row);
+    uint4 hi, lo;
+    pack_plane<0>(re, hi, lo);
+    *reinterpret_cast<uint4*>(o) = hi;
+    *reinterpret_cast<uint4*>(o + HWD) = lo;
+    pack_plane<0>(im, hi, lo);
+    *reinterpret_cast<uint4*>(o + 2 * HWD) = hi;
+    *reinterpret_cast<uint4*>(o + 3 * HWD) = lo;
+    pack_plane<0>(sm, hi, lo);
+    *reinterpret_cast<uint4*>(o + 4 * HWD) = hi;
+    *reinterpret_cast<uint4*>(o + 5 * HWD) = lo;
+  }
+}
+
+// Columns of M (c64 rows [N][ldm], columns < nb valid) -> plane words
+// [nb_pad/128][nstN][6][HWD] (re, im, re + im; hi, lo) with k running over the
+// rows of M; zero for columns >= nb and rows >= N.
+__global__ void tile_cols3_kernel(int N, int nb, int nTb, int nst, const float2* __restrict__ M, long ldm,
+                                  uint32_t* __restrict__ out) {
+  const size_t total = (size_t)nTb * nst * 2 * TR;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(e % TR);
+    const int h = (int)((e / TR) % 2);
+    const size_t bs = e / (2 * TR);
+    const int st = (int)(bs % nst), blk = (int)(bs / nst);
+    const int c = blk * TR + col;
+    const int r0 = st * TK + 8 * h;
+    float re[8], im[8], sm[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float2 x = make_float2(0.f, 0.f);
+      if (c < nb && r0 + q < N) x = M[(size_t)(r0 + q) * ldm + c];
+      re[q] = x.x;
+      im[q] = x.y;
+      sm[q] = x.x + x.y;
+    }
+    uint32_t* o = out + bs * 6 * HWD + lane_off3(h, col);
+    uint4 hi, lo;
+    pack_plane<0>(re, hi, lo);
+    *reinterpret_cast<uint4*>(o) = hi;
+    *reinterpret_cast<uint4*>(o + HWD) = lo;
+    pack_plane<0>(im, hi, lo);
+    *reinterpret_cast<uint4*>(o + 2 * HWD) = hi;
+    *reinterpret_cast<uint4*>(o + 3 * HWD) = lo;
+    pack_plane<0>(sm, hi, lo);
+    *reinterpret_cast<uint4*>(o + 4 * HWD) = hi;
+    *reinterpret_cast<uint4*>(o + 5 * HWD) = lo;
+  }
+}
+
 // q[n'] = Re sum_mu conj(M[mu][n']) Y[mu][n'] in two fixed-order passes: a
 // workgroup covers 32 columns and one chunk of rows (8 row groups of 32
 // lanes, combined in LDS), then the chunks are summed in order.
@@ -2451,10 +2528,12 @@ struct SigmaDims {
     nbp = cdiv(nb, TN) * TN;
     cols = g * nbp;
     nTb = cols / TR;
+    // word arrays sized for the larger of the two GEMM cores' layouts
+    // (four-product: 8 / 4 HWD per block-stage for A / B; three-product: 6)
     u_words = (size_t)nI * nstR * 4 * WD;
-    q_words = (size_t)(nbp / TR) * nstR * 2 * WD;   // pair products of one state
+    q_words = (size_t)(nbp / TR) * nstR * 6 * HWD;   // pair products of one state
     m_c64 = (size_t)N * cols;
-    mt_words = (size_t)nTb * nstN * 2 * WD;
+    mt_words = (size_t)nTb * nstN * 6 * HWD;
     w_words = (size_t)nI * nstN * 4 * WD;
     part = (size_t)CD_CHUNKS * cols;
   }
@@ -2489,11 +2568,58 @@ int tiled_sigma_quadforms(hipStream_t s, int N, int R, int nb, int g, int n_mesh
   const int rows_per_chunk = cdiv(N, CD_CHUNKS);
   int st;
   TiledDims td(N, R, nb, 0);
-  if (tile_u && (st = launch_tile_u(s, td, N, R, U, Uw)) != GW_OK) return st;
   // the padding columns of every state's block stay zero
   hipLaunchKernelGGL(zero_u32_kernel, dim3(stream_blocks(d.m_c64 * 2)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(M), d.m_c64 * 2);
   GW_LAUNCHED("zero_u32_kernel");
+  if (g_complex_product == 3) {
+    // three-multiplication core: U and product planes (re, im, re + im), the
+    // projections, then per frequency Y = W^c M on W^c and M planes
+    if (tile_u && (st = launch_tile_u3<0>(s, td, N, R, U, nullptr, Uw)) != GW_OK) return st;
+    for (int i = 0; i < g; ++i) {
+      if ((st = launch_pair_product3<0>(s, td, R, psi_state[i], psi_all[i], nb, 0, nb, nullptr, nullptr, nullptr, Q)) !=
+          GW_OK)
+        return st;
+      GemmArgs a{};
+      set_projection3(a, td, Uw, Q, N, nb);
+      a.M = M + (size_t)i * d.nbp;
+      a.ldm = d.cols;
+      if ((st = launch_gemm3m<OUT_ROWS, 0>(s, a, d.nI * a.nTj, "sigma_project_kernel")) != GW_OK) return st;
+    }
+    hipLaunchKernelGGL(tile_cols3_kernel, dim3(stream_blocks((size_t)d.nTb * d.nstN * 2 * TR)), dim3(256), 0, s, N,
+                       d.cols, d.nTb, d.nstN, M, (long)d.cols, Mt);
+    GW_LAUNCHED("tile_cols3_kernel");
+    for (int j = 0; j < n_mesh; ++j) {
+      hipLaunchKernelGGL(tile_wc3_kernel, dim3(stream_blocks((size_t)d.nI * d.nstN * 2 * TR)), dim3(256), 0, s, N,
+                         d.nI, d.nstN, W + (size_t)j * N * N, v, Ww);
+      GW_LAUNCHED("tile_wc3_kernel");
+      GemmArgs b{};
+      b.A = Ww;
+      b.B = Mt;
+      b.a_words3 = 6;
+      b.b_words3 = 6;
+      b.b_sum3 = 4;
+      b.sigma3 = -1.f;
+      b.nst = d.nstN;
+      b.a_bstride = (size_t)d.nstN * 6 * HWD;
+      b.b_bstride = (size_t)d.nstN * 6 * HWD;
+      b.nI = d.nI;
+      b.nTj = d.cols / TN;
+      b.N = N;
+      b.T = d.cols;
+      b.M = Y;
+      b.ldm = d.cols;
+      if ((st = launch_gemm3m<OUT_ROWS, 0>(s, b, d.nI * b.nTj, "sigma_wm_kernel")) != GW_OK) return st;
+      hipLaunchKernelGGL(coldot_f32_kernel, dim3(cdiv(d.cols, 32), CD_CHUNKS), dim3(256), 0, s, N, d.cols, M, Y,
+                         (long)d.cols, rows_per_chunk, part);
+      GW_LAUNCHED("coldot_f32_kernel");
+      hipLaunchKernelGGL(coldot_reduce_kernel, dim3(cdiv(d.cols, 256)), dim3(256), 0, s, d.cols, CD_CHUNKS, part,
+                         q + (size_t)j * d.cols);
+      GW_LAUNCHED("coldot_reduce_kernel");
+    }
+    return GW_OK;
+  }
+  if (tile_u && (st = launch_tile_u(s, td, N, R, U, Uw)) != GW_OK) return st;
   for (int i = 0; i < g; ++i) {
     if ((st = launch_pair_product(s, td, R, psi_state[i], psi_all[i], nb, 0, nb, Q)) != GW_OK) return st;
     GemmArgs a{};

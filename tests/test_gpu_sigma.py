@@ -67,11 +67,14 @@ def test_sigma_fp64_config1(lib):
     assert np.all(s[:, out > 0].imag < 0)
 
 
+@pytest.mark.parametrize("cp", [3, 4])
 @pytest.mark.parametrize("shape", [
     dict(n_k=2, n_b=60, R=1000, N=300, n_occ=3, n_unocc=150),
     dict(n_k=3, n_b=64, R=513, N=129, n_occ=2, n_unocc=63),
 ])
-def test_sigma_split_bf16(lib, shape):
+def test_sigma_split_bf16(lib, shape, cp):
+    """Split BF16 on both GEMM cores (complex_product 3: the three-product
+    six-slot core, the default; 4: the four-product core) against the oracle."""
     import torch
     inp = gwsynth.generate(gwsynth.make_shape(**shape), seed=5, omega=gwsynth.omega_mesh("m16"))
     n_occ = shape["n_occ"]
@@ -86,11 +89,15 @@ def test_sigma_split_bf16(lib, shape):
     Ws = _gpu_W(lib, torch.from_numpy(U64).to("cuda"), torch.from_numpy(psi64).to("cuda"), inp.eps, mesh, n_occ, v)
     U32 = torch.from_numpy(inp.U).to("cuda", torch.complex64)
     psi32 = torch.from_numpy(inp.psi).to("cuda", torch.complex64)
-    sig = lib.gw_sigma_c(U32, psi32, inp.eps, Ws, v, mesh, out, states, mu, precision="split_bf16")
-    torch.cuda.synchronize()
+    try:
+        lib.gw_set_tuning("complex_product", cp)
+        sig = lib.gw_sigma_c(U32, psi32, inp.eps, Ws, v, mesh, out, states, mu, precision="split_bf16")
+        torch.cuda.synchronize()
+    finally:
+        lib.gw_set_tuning("complex_product", 3)
     ref = _oracle(U64, psi64, inp.eps, mesh, n_occ, inp.v, out, states, mu)
     err = _rel(sig.cpu().numpy(), ref)
-    print(f"sigma_c split_bf16 {shape}: rel err {err:.2e}")
+    print(f"sigma_c split_bf16 {shape}, complex_product {cp}: rel err {err:.2e}")
     assert err < 1e-4
 
 
