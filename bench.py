@@ -530,6 +530,21 @@ def summarize_pmc(a) -> int:
     return 0
 
 
+def measured_traffic(traffic_file: str, kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from a counter summary written by
+    --summarize-pmc, or None unless the summary is for this kernel and
+    workload and was measured on the current GEMM sources (source hash)."""
+    try:
+        with open(traffic_file) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel") == kernel and tr.get("source_hash") == kernel_source_hash() and \
+                tr.get("workload") == workload:
+            return float(tr["bytes_per_launch"])
+    except (OSError, ValueError, KeyError, TypeError):
+        pass
+    return None
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -750,15 +765,8 @@ def main() -> int:
     alg_per_launch = per_step[dom] * a.steps / max(1, dk["launches"])
     achieved = alg_per_launch / (avg_ms * 1e-3) / 1e12
     peak_dtype = "fp64" if dom == "update_kernel" else {"bf16": "bf16", "f16": "fp16", "f16s": "fp16", "f32": "fp32"}[pre]
-    traffic = None
-    traffic_file = a.traffic or os.path.join(ROOT, "profiles", f"traffic_{a.workload}.json")
-    try:
-        with open(traffic_file) as fh:
-            tr = json.load(fh)
-        if tr.get("kernel") == dom and tr.get("source_hash") == kernel_source_hash() and tr.get("workload") == a.workload:
-            traffic = tr["bytes_per_launch"]
-    except (OSError, ValueError, KeyError):
-        traffic = None
+    traffic = measured_traffic(a.traffic or os.path.join(ROOT, "profiles", f"traffic_{a.workload}.json"), dom,
+                               a.workload)
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[peak_dtype],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[peak_dtype], 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 4), "alg_flops_per_launch": alg_per_launch,

@@ -79,3 +79,58 @@ def test_block_error_estimate_weights_diagonal_and_off_diagonal():
     est = np.array(be["full_matrix_estimate_per_omega"])
     assert np.all(np.abs(est / full - 1) < 0.15), (est, full)
     assert be["max_rel_fro_err"] < 0.5 * full.min()                    # the plain block error is biased low
+
+
+def test_pmc_summary_names_the_six_slot_projection(tmp_path):
+    """The projection of the default core is the OUT_TILED instance of the
+    six-slot kernel (first template argument 0); the row-projection and
+    accumulation instances are not taken for it."""
+    rows = "void gw::(anonymous namespace)::gemm3r_kernel<1, 0, 4, false>(gw::(anonymous namespace)::GemmArgs)"
+    proj = "void gw::(anonymous namespace)::gemm3r_kernel<0, 0, 4, false>(gw::(anonymous namespace)::GemmArgs)"
+    herk = "void gw::(anonymous namespace)::gemm3r_kernel<2, 0, 4, false>(gw::(anonymous namespace)::GemmArgs)"
+    copy = "__amd_rocclr_copyBuffer"
+    d = [str(tmp_path / x) for x in ("f", "w", "cf", "cw")]
+    _write(d[0], "FETCH_SIZE", [(rows, 7.0), (proj, 100.0), (herk, 50.0)])
+    _write(d[1], "WRITE_SIZE", [(rows, 1.0), (proj, 10.0), (herk, 4.0)])
+    _write(d[2], "FETCH_SIZE", [(copy, 524288.0)])
+    _write(d[3], "WRITE_SIZE", [(copy, 1048576.0)])
+    out = tmp_path / "traffic.json"
+    r = _bench("--summarize-pmc", *d, "--traffic", str(out))
+    assert r.returncode == 0, r.stderr
+    t = json.loads(out.read_text())
+    assert t["symbol"] == "gemm3r_kernel<0, 0, 4, false>"
+    assert t["bytes_per_launch"] == 100.0 * 1024 * 2.0 + 10.0 * 1024
+
+
+def test_traffic_reported_only_for_the_measured_sources(tmp_path):
+    """A counter summary gives the roofline's traffic only for the kernel and
+    workload it was measured on and while the GEMM sources hash to the
+    measured build; anything else (other hash, kernel or workload, a missing
+    or unreadable file) gives None rather than a stale figure."""
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.kernel_source_hash()
+    good = {"workload": "c5", "kernel": "project_bf16_kernel", "source_hash": h, "bytes_per_launch": 1.5e11}
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps(good))
+    assert bench.measured_traffic(str(f), "project_bf16_kernel", "c5") == 1.5e11
+    assert bench.measured_traffic(str(f), "herk_bf16_kernel", "c5") is None
+    assert bench.measured_traffic(str(f), "project_bf16_kernel", "c3") is None
+    f.write_text(json.dumps(dict(good, source_hash="0" * 16)))
+    assert bench.measured_traffic(str(f), "project_bf16_kernel", "c5") is None
+    f.write_text("{not json")
+    assert bench.measured_traffic(str(f), "project_bf16_kernel", "c5") is None
+    assert bench.measured_traffic(str(tmp_path / "missing.json"), "project_bf16_kernel", "c5") is None
+
+
+def test_committed_traffic_summary_matches_the_sources():
+    """profiles/traffic_c5.json was measured on the GEMM sources in the tree
+    (a kernel edit without new counter passes makes this fail, and the bench
+    then reports traffic as null)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(os.path.join(ROOT, "profiles", "traffic_c5.json")) as fh:
+        t = json.load(fh)
+    assert t["workload"] == "c5" and t["kernel"] == "project_bf16_kernel"
+    assert t["source_hash"] == bench.kernel_source_hash()
+    assert bench.measured_traffic(os.path.join(ROOT, "profiles", "traffic_c5.json"), "project_bf16_kernel", "c5") > 0
